@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs: droplet geometries and channel parameters.
+
+This module is the ONLY code shared by the GPU path's tests/benchmarks and the
+oracle.  It builds initial component-density fields (rho1, rho2, u) and model
+parameters; it contains none of the lattice Boltzmann arithmetic.
+
+The paper's workloads (droplet-packed microchannels, flowing emulsions in a
+flow-focuser outlet) come without lattice-unit geometry or data, so these
+stand-ins follow the configurations used throughout this project:
+
+* ``laplace_droplet``  -- one static droplet, 2-D periodic box (Laplace check)
+* ``hex_channel_3d``   -- 3-D wall-bounded channel packed with spherical
+  droplets on a jittered hexagonal lattice (x-y plane, stacked along z)
+* ``channel_2d``       -- one 2-D wall-bounded channel with a hexagonal
+  droplet packing, parameters drawn from ``batch_specs``
+* ``two_droplets_2d``  -- two droplets separated by a thin film (NCI check)
+
+All randomness is numpy PCG64 with the seed given.  Interfaces are initialised
+with the profile psi0 = tanh((R - r)/2) and rho1 = (1 + psi0)/2,
+rho2 = (1 - psi0)/2, where r is the distance to the nearest droplet centre
+(periodic images in the periodic directions).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, asdict
+
+import numpy as np
+
+SIGMA0 = 1.0 / 90.0  # surface tension held fixed across the sweep (lattice units)
+
+
+def _profile(psi0: np.ndarray):
+    return 0.5 * (1.0 + psi0), 0.5 * (1.0 - psi0)
+
+
+def _droplet_psi(shape, centres, radii, periodic):
+    """psi0 = max over droplets of tanh((R - r)/2); ``shape`` is (nz, ny, nx)
+    (x fastest in memory), centres are (x, y, z) rows."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    psi = np.full(shape, -1.0)
+    dims = (nx, ny, nz)
+    for (cx, cy, cz), R in zip(centres, radii):
+        d2 = np.zeros(shape)
+        for a, (coord, cc) in enumerate(((x, cx), (y, cy), (z, cz))):
+            d = coord - cc
+            if periodic[a]:
+                L = dims[a]
+                d = d - L * np.round(d / L)
+            d2 = d2 + d * d
+        psi = np.maximum(psi, np.tanh((R - np.sqrt(d2)) / 2.0))
+    return psi
+
+
+@dataclass
+class Case:
+    """One workload: parameter dict (lb_params fields) and initial fields."""
+    params: dict
+    rho1: np.ndarray
+    rho2: np.ndarray
+    u: np.ndarray | None = None
+    info: dict | None = None
+
+    @property
+    def N(self):
+        return self.rho1.size
+
+
+def base_params(**kw) -> dict:
+    p = dict(lattice=0, nx=128, ny=64, nz=1, walls_y=0, tau=1.0, A_s=0.05, beta=0.7,
+             A_nci=0.005, h_min=2.0, h_max=4.0, force=(0.0, 0.0, 0.0))
+    p.update(kw)
+    return p
+
+
+def laplace_droplet(nx=128, ny=64, R=16.0, centre=None, **kw) -> Case:
+    """One droplet of radius R centred in a periodic D2Q9 box."""
+    cx, cy = centre if centre is not None else (nx // 2, ny // 2)
+    psi = _droplet_psi((1, ny, nx), [(cx, cy, 0)], [R], (True, True, True))
+    r1, r2 = _profile(psi.ravel())
+    return Case(base_params(nx=nx, ny=ny, **kw), r1, r2, None, {"R": R, "centre": (cx, cy)})
+
+
+def two_droplets_2d(nx=96, ny=48, R=10.0, gap=1.0, jitter=0.0, seed=0, **kw) -> Case:
+    """Two droplets on the x axis whose surfaces are ``gap`` nodes apart."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = 2 * R + gap
+    cs = [(nx / 2 - d / 2, ny / 2, 0.0), (nx / 2 + d / 2, ny / 2, 0.0)]
+    cs = [(x + jitter * rng.uniform(-1, 1), y + jitter * rng.uniform(-1, 1), 0.0) for x, y, _ in cs]
+    psi = _droplet_psi((1, ny, nx), cs, [R, R], (True, True, True))
+    r1, r2 = _profile(psi.ravel())
+    return Case(base_params(nx=nx, ny=ny, **kw), r1, r2, None, {"centres": cs})
+
+
+def _hex_rows(L_x, y_lo, y_hi, a):
+    """Hexagonal lattice of centres in [0, L_x) x [y_lo, y_hi]: rows along x
+    with spacing snapped so that an integer number fits the periodic length."""
+    n_x = max(1, int(round(L_x / a)))
+    a_x = L_x / n_x
+    pitch = a_x * math.sqrt(3.0) / 2.0
+    rows = []
+    y = y_lo
+    r = 0
+    while y <= y_hi + 1e-9:
+        off = 0.5 * a_x * (r % 2)
+        rows.append([(off + a_x * i, y) for i in range(n_x)])
+        y += pitch
+        r += 1
+    return rows, a_x, pitch
+
+
+def hex_channel_3d(nx=256, ny=64, nz=64, R=7.0, frac=0.8, z_pitch=16.0, jitter=0.5, seed=2,
+                   force=1e-5, **kw) -> Case:
+    """Wall-bounded D3Q27 channel (walls at y=0, ny-1; periodic x, z) packed
+    with spheres of radius R: hexagonal in the x-y plane at planar area
+    fraction ``frac`` (spacing a from (2 pi/sqrt 3)(R/a)^2 = frac, snapped to
+    the periodic length), layers along z at ``z_pitch``, uniform jitter of
+    +-``jitter`` nodes per coordinate.  Centres stay >= R+1 from the walls."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = R * math.sqrt(2.0 * math.pi / (math.sqrt(3.0) * frac))
+    rows, a_x, pitch = _hex_rows(nx, 1 + R + 1, ny - 2 - R - 1, a)
+    n_layers = max(1, int(nz // z_pitch))
+    centres = []
+    for l in range(n_layers):
+        zc = z_pitch / 2 + l * z_pitch
+        for row in rows:
+            for (xc, yc) in row:
+                centres.append((xc + jitter * rng.uniform(-1, 1), yc + jitter * rng.uniform(-1, 1),
+                                zc + jitter * rng.uniform(-1, 1)))
+    psi = _droplet_psi((nz, ny, nx), centres, [R] * len(centres), (True, False, True))
+    psi[:, 0, :] = -1.0
+    psi[:, ny - 1, :] = -1.0
+    r1, r2 = _profile(psi.ravel())
+    p = base_params(lattice=1, nx=nx, ny=ny, nz=nz, walls_y=1, force=(force, 0.0, 0.0), **kw)
+    vol = len(centres) * 4.0 / 3.0 * math.pi * R ** 3 / (nx * (ny - 2) * nz)
+    return Case(p, r1, r2, None, {"n_droplets": len(centres), "a_x": a_x, "row_pitch": pitch,
+                                  "volume_fraction": vol})
+
+
+@dataclass
+class ChannelSpec:
+    """Parameters of one 2-D channel of the batched sweep."""
+    seed: int
+    Lx: int
+    Ly: int
+    phi_p: float
+    G_p: float
+    A_nci: float
+    R: float
+    tau: float
+    A_s: float
+
+    def as_dict(self):
+        return asdict(self)
+
+
+def channel_spec(seed: int, Lx=None, Ly=None) -> ChannelSpec:
+    """Draw one channel: Lx ~ U{256..1024}, Ly ~ U{64..160}, packing
+    phi_p ~ U[0.7, 0.9], pressure gradient G_p ~ logU[1e-6, 1e-4],
+    A_nci ~ U[0, 0.05], droplet radius R ~ U{10..20}.  tau is raised so that
+    the Poiseuille peak speed 3 G_p H^2 / (8 (tau - 1/2)) stays <= 0.05, and
+    A_s = 9 sigma0 / (2 tau) keeps the surface tension at sigma0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lx = int(rng.integers(256, 1025))
+    ly = int(rng.integers(64, 161))
+    phi_p = float(rng.uniform(0.7, 0.9))
+    G_p = float(10 ** rng.uniform(-6, -4))
+    A_nci = float(rng.uniform(0.0, 0.05))
+    R = float(rng.integers(10, 21))
+    Lx = lx if Lx is None else Lx
+    Ly = ly if Ly is None else Ly
+    H = Ly - 2
+    tau = max(1.0, 0.5 + 3.0 * G_p * H * H / (8.0 * 0.05))
+    A_s = 9.0 * SIGMA0 / (2.0 * tau)
+    return ChannelSpec(seed, Lx, Ly, phi_p, G_p, A_nci, R, tau, A_s)
+
+
+def batch_specs(master_seed=3, n=64):
+    """Per-channel seeds drawn from the master seed, then ``channel_spec``."""
+    rng = np.random.Generator(np.random.PCG64(master_seed))
+    seeds = rng.integers(0, 2 ** 31 - 1, size=n)
+    return [channel_spec(int(s)) for s in seeds]
+
+
+def channel_2d(spec: ChannelSpec, jitter=0.5) -> Case:
+    """Wall-bounded D2Q9 channel with a jittered hexagonal droplet packing."""
+    rng = np.random.Generator(np.random.PCG64(spec.seed + 1))
+    R = spec.R
+    a = R * math.sqrt(2.0 * math.pi / (math.sqrt(3.0) * spec.phi_p))
+    rows, a_x, pitch = _hex_rows(spec.Lx, 1 + R + 1, spec.Ly - 2 - R - 1, a)
+    centres = []
+    for row in rows:
+        for (xc, yc) in row:
+            centres.append((xc + jitter * rng.uniform(-1, 1), yc + jitter * rng.uniform(-1, 1), 0.0))
+    psi = _droplet_psi((1, spec.Ly, spec.Lx), centres, [R] * len(centres), (True, False, True))
+    psi[:, 0, :] = -1.0
+    psi[:, spec.Ly - 1, :] = -1.0
+    r1, r2 = _profile(psi.ravel())
+    p = base_params(lattice=0, nx=spec.Lx, ny=spec.Ly, nz=1, walls_y=1, tau=spec.tau,
+                    A_s=spec.A_s, A_nci=spec.A_nci, force=(spec.G_p, 0.0, 0.0))
+    return Case(p, r1, r2, None, {"n_droplets": len(centres), "spec": spec.as_dict()})
+
+
+def poiseuille_2d(nx=4, ny=34, force=1e-6, tau=1.0) -> Case:
+    """Single-phase (rho1 = 1, rho2 = 0) wall-bounded channel at rest."""
+    N = nx * ny
+    r1 = np.ones(N)
+    r2 = np.zeros(N)
+    return Case(base_params(nx=nx, ny=ny, walls_y=1, tau=tau, force=(force, 0.0, 0.0)), r1, r2)
+
+
+def random_fields(p: dict, seed=0, amp=0.05, umax=0.02) -> Case:
+    """Smooth-ish random two-component fields (for invariant and parity tests)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    dim = 2 if p["lattice"] == 0 else 3
+    psi = np.tanh(3.0 * rng.uniform(-1, 1, (nz, ny, nx)))
+    rho = 1.0 + amp * rng.uniform(-1, 1, (nz, ny, nx))
+    r1 = (rho * 0.5 * (1 + psi)).ravel()
+    r2 = (rho * 0.5 * (1 - psi)).ravel()
+    u = umax * rng.uniform(-1, 1, (dim, nx * ny * nz))
+    return Case(dict(p), r1, r2, u)
