@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the colour-gradient + NCI lattice Boltzmann step.
+
+Workload (default): 3-D D3Q27 droplet-packed channel 256 x 64 x 64, walls at
+y = 0 and 63, periodic x and z, 272 jittered droplets of radius 7 on a
+hexagonal packing, body force 1e-5 along x, NCI on (A = 0.005, h_min = 2,
+h_max = 4), tau = 1, FP32 deviation storage.  One step = k_phase + k_main over
+the whole lattice; the state is resident in HBM before timing starts.
+
+Prints ONE JSON line with MLUPS (fluid nodes), the roofline of the dominant
+kernel (k_main) measured with HIP events on the library's stream, the
+achievable-bandwidth reference of a plain copy kernel, and the FP64 oracle
+timed on the host cores over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS/GPU + HBM roofline %; steps-to-steady-state plain vs learned warm start"
+HBM_PEAK_GBPS = 8000.0
+# bytes of the paper's two-population state read + written once per fluid
+# node-update plus psi written and read once (FP32 populations)
+B_ALG_TWO_POP = {2: 2 * 2 * 9 * 4 + 8, 3: 2 * 2 * 27 * 4 + 8}
+
+
+def main_kernel_bytes(dim: int, storage: str) -> int:
+    """Compulsory HBM bytes per fluid node of one k_main launch in the
+    library's layout: state read once (s_i, a, B) + state written once + psi
+    read once."""
+    Q = 9 if dim == 2 else 27
+    s_b = 2 if storage in ("fp16", "bf16") else 4
+    r_b = 8 if storage == "fp32" else 4
+    rest_extra = 4 if storage in ("fp16", "bf16") else 0  # FP32 rest slot
+    state = Q * s_b + rest_extra + r_b + 4 * dim
+    return 2 * state + r_b
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2003_11069_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hpp", ".hip")) and f.startswith("lb_"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(name: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
+    when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256:\s*(\w+)", txt)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(case, budget_s: float):
+    """The FP64 oracle as it stands, stepped on the host until ~budget_s."""
+    import oracle
+    p = oracle.Params(**{k: v for k, v in case.params.items() if k in oracle.Params.__dataclass_fields__})
+    o = oracle.Oracle(p)
+    o.init_fields(case.rho1, case.rho2, case.u)
+    o.step(1)  # first-touch of the arrays
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 1000:
+            break
+    fluid = case.params["nx"] * (case.params["ny"] - 2 * case.params["walls_y"]) * case.params["nz"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": fluid * n / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{n} steps of the same workload after 1 warm-up step, {el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp32_f32"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU domain decomposition is not built)"}))
+        return 2
+
+    import numpy as np
+    import synth
+    import paper_2003_11069_amd as P
+    from paper_2003_11069_amd.lb import copy_probe
+
+    case = synth.hex_channel_3d()
+    prm = case.params
+    dim = 3
+    fluid = prm["nx"] * (prm["ny"] - 2) * prm["nz"]
+    L = P.Lattice(P.Params.from_dict(prm, storage=P.STORAGE[a.storage]))
+    L.init_fields(case.rho1, case.rho2, case.u)
+    L.step(a.warmup)
+    L.kernel_times()  # drains the stream
+    L.profile(True)
+    t0 = time.perf_counter()
+    L.step(a.steps)
+    kt = L.kernel_times()  # synchronises
+    t1 = time.perf_counter()
+    L.profile(False)
+    ob = L.observables()
+    el = t1 - t0
+    mlups = fluid * a.steps / el / 1e6
+    ms_main = kt["ms_main"] / max(kt["launches"], 1)
+    ms_phase = kt["ms_phase"] / max(kt["launches"], 1)
+    b_main = main_kernel_bytes(dim, a.storage)
+    achieved = b_main * fluid / (ms_main * 1e-3) / 1e9
+    cp = copy_probe(1 << 30, iters=20)
+    traffic = traffic_from_profile(f"k_main_d3q27_{a.storage}_channel256x64x64.txt")
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(el / a.steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f64", "fp16": "f32", "bf16": "f32", "fp32_f32": "f32"}[a.storage],
+        "data": "synthetic (seeded droplet packing)",
+        "config": {"workload": "D3Q27 droplet channel 256x64x64, walls y, 272 droplets R=7, "
+                               "body force 1e-5, NCI A=0.005 h 2..4, tau=1",
+                   "lattice": "D3Q27", "nx": prm["nx"], "ny": prm["ny"], "nz": prm["nz"],
+                   "fluid_nodes": fluid, "storage": a.storage},
+        "roofline": {"bound": "hbm", "kernel": "k_main", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "alg_bytes_per_node": b_main,
+                     "avg_ms": round(ms_main, 5), "launches": kt["launches"]},
+        "step": {"k_phase_avg_ms": round(ms_phase, 5), "k_main_avg_ms": round(ms_main, 5),
+                 "effective_GBps_two_pop_state": round(B_ALG_TWO_POP[dim] * mlups * 1e6 / 1e9, 1),
+                 "effective_frac_two_pop_state": round(B_ALG_TWO_POP[dim] * mlups * 1e6 / 1e9
+                                                       / HBM_PEAK_GBPS, 4)},
+        "copy_probe": {"GBps": round(cp["GBps"], 1), "frac_of_peak": round(cp["GBps"] / HBM_PEAK_GBPS, 4),
+                       "k_main_frac_of_copy": round(achieved / cp["GBps"], 4)},
+        "obs": {"Q": ob["Q"], "Q_d": ob["Q_d"], "umax": ob["umax"]},
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,174 @@
+/*
+ * lbnci.h -- C ABI of the MI355X colour-gradient lattice Boltzmann library
+ * with near-contact interactions (NCI).
+ *
+ * The method is the one in the Materials and Methods section of Montessori,
+ * Tiribocchi, Bonaccorso, Lauricella & Succi, "Lattice Boltzmann simulations
+ * capture the multiscale physics of soft flowing crystals" (2019):
+ *   Eq. (CGLBE)   two population sets f_i^k (k = 1 dispersed, 2 continuous)
+ *                 streamed along c_i with dt = 1 on D3Q27 (D2Q9 in 2-D);
+ *   moments       rho^k = sum_i f_i^k, rho u = sum_k sum_i c_i f_i^k;
+ *   collision     Omega = Omega3[Omega1 + Omega2]: single-tau BGK relaxation
+ *                 (mixture viscosity), perturbation (interfacial tension),
+ *                 Latva-Kokko recolouring (segregation);
+ *   Eq. (near_c)  F_rep = -A_h[h(x)] n delta_I, n = -grad psi/|grad psi|,
+ *                 psi = (rho1-rho2)/(rho1+rho2), delta_I = |grad psi|/2,
+ *                 A_h = A (h <= h_min), A (h_min/h)^3 (h <= h_max), 0 beyond;
+ *   forcing       exact difference method, F = body force + F_rep.
+ * The operator formulas the paper only names, wall treatment and tie rules
+ * are fixed readings, documented with the project.
+ *
+ * Conventions
+ *   - Node index n = x + nx*(y + ny*z), x fastest, for every array.
+ *   - Host arrays are caller-owned; they are copied synchronously.
+ *   - Device state is owned by the handle (hipMalloc at lb_create).
+ *   - lb_step is asynchronous on the handle's HIP stream; lb_observables,
+ *     lb_get_fields and lb_get_populations synchronise that stream.
+ *   - Every call returns 0 (LB_OK) or a negative LB_E* code; the message of
+ *     the last failure on the calling thread is lb_last_error().
+ *   - Wall rows (walls_y = 1: y = 0 and y = ny-1) are solid.  Their entries in
+ *     field/population arrays are ignored on input and 0 on output.
+ */
+#ifndef LBNCI_H
+#define LBNCI_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_EINVAL (-1)   /* invalid argument or parameter                 */
+#define LB_ENOMEM (-2)   /* device or host allocation failed              */
+#define LB_EDEVICE (-3)  /* a HIP runtime call failed                     */
+#define LB_ENUMERIC (-4) /* NaN/Inf detected in the observables            */
+#define LB_ESTATE (-5)   /* call out of order (e.g. step before init)      */
+
+typedef struct lb_handle lb_handle; /* opaque, owned by the library */
+
+typedef enum { LB_D2Q9 = 0, LB_D3Q27 = 1 } lb_lattice;
+
+/* Population storage (stored quantity: deviation s_i = f_i/w_i - 1 of the
+ * post-collision total population from its lattice weight, plus per-node
+ * colour scalars from which both components are rebuilt exactly):
+ *   LB_STORE_FP32      s_i in FP32, colour fraction in FP64, FP64 arithmetic
+ *   LB_STORE_FP16_DEV  s_i in FP16 (rest direction FP32, closing the node
+ *                      mass exactly), FP32 arithmetic
+ *   LB_STORE_BF16_DEV  as FP16_DEV with BF16
+ *   LB_STORE_FP32_F32  s_i in FP32 with FP32 arithmetic throughout        */
+typedef enum {
+  LB_STORE_FP32 = 0,
+  LB_STORE_FP16_DEV = 1,
+  LB_STORE_BF16_DEV = 2,
+  LB_STORE_FP32_F32 = 3
+} lb_storage;
+
+typedef struct {
+  int32_t lattice;     /* lb_lattice                                           */
+  int32_t nx, ny, nz;  /* lattice size; nz == 1 for D2Q9                       */
+  int32_t walls_y;     /* 0: periodic in y; 1: half-way bounce-back walls at
+                          y = 0 and y = ny-1 (x and z always periodic)         */
+  double tau;          /* BGK relaxation time (> 1/2); nu = (tau - 1/2)/3      */
+  double A_s;          /* perturbation amplitude; sigma = 2 A_s tau / 9        */
+  double beta;         /* recolouring parameter, [0, 1]                        */
+  double A_nci;        /* NCI strength A (>= 0; 0 switches NCI off)            */
+  double h_min, h_max; /* NCI range in lattice spacings (paper: 2 and 4),
+                          0 < h_min <= h_max <= 4                              */
+  double force[3];     /* uniform body-force density (= -grad p)              */
+  int32_t storage;     /* lb_storage                                           */
+  int32_t obs_every;   /* record observables every k steps inside lb_step
+                          (feeds the convergence test); 0 = only on request    */
+  int32_t conv_window; /* convergence window W in recorded samples (0 = off)  */
+  int32_t conv_m;      /* consecutive windows required                         */
+  double conv_eps;     /* relative change of the windowed flow rate           */
+} lb_params;
+
+/* Observables of the current state, accumulated in FP64 in a fixed order:
+ *   mass[k]  = sum_x rho^k
+ *   mom      = sum_x (j + F/2)             (physical momentum, EDM)
+ *   Q        = sum_x u_x / nx              (flow rate through a cross-section)
+ *   Q_d      = sum_x (rho1/rho) u_x / nx   (dispersed-phase flow rate)
+ *   umax     = max_x |u|,  u = (j + F/2)/rho
+ *   converged: windowed-Q test satisfied (conv_window > 0)
+ *   flags    : bit 0 NaN/Inf seen                                          */
+typedef struct {
+  int64_t step;
+  double mass[2];
+  double mom[3];
+  double Q, Q_d, umax;
+  double Q_window;     /* mean Q over the last complete window (0 if none) */
+  int32_t converged;
+  int32_t flags;
+} lb_obs;
+
+/* Creates a lattice on the current HIP device.  hip_stream: a hipStream_t
+ * (NULL = default stream) on which all work of the handle is enqueued.
+ * Errors: LB_EINVAL (tau <= 1/2, beta outside [0,1], sizes <= 0, nz != 1 with
+ * D2Q9, walls with ny < 3, h_min > h_max, h_max > 4 or h_min <= 0, A_nci < 0,
+ * unknown storage), LB_ENOMEM, LB_EDEVICE. */
+int lb_create(const lb_params *p, void *hip_stream, lb_handle **out);
+
+/* Initial state f_i^k(x,0) = E_i(rho^k(x), u(x)) with the second-order
+ * equilibrium, computed on the host in FP64.  rho1, rho2: N doubles each;
+ * u: dim*N doubles (u_x block, u_y block[, u_z block]) or NULL for rest.
+ * Errors: LB_EINVAL on negative/NaN densities or rho1+rho2 <= 0 at a fluid
+ * node.  Resets the step counter and the convergence state. */
+int lb_init_fields(lb_handle *h, const double *rho1, const double *rho2, const double *u);
+
+/* Arbitrary initial state: f1, f2 hold Q*N doubles each in layout [i][n]
+ * with the direction order of lb_lattice_tables.  Errors as lb_init_fields. */
+int lb_set_populations(lb_handle *h, const double *f1, const double *f2);
+
+/* Advance n >= 0 steps (collide, then pull-stream).  Asynchronous.
+ * Errors: LB_ESTATE before initialisation, LB_EDEVICE on launch failure. */
+int lb_step(lb_handle *h, int64_t n);
+
+/* Observables of the current state (synchronises the stream).
+ * Returns LB_ENUMERIC if a NaN/Inf was seen (out is still filled). */
+int lb_observables(lb_handle *h, lb_obs *out);
+
+/* Current fields: rho1, rho2 (N doubles each) and the physical velocity
+ * u = (j + F/2)/rho (dim*N doubles), F the force of the next collision. */
+int lb_get_fields(lb_handle *h, double *rho1, double *rho2, double *u);
+
+/* Current post-streaming populations f1, f2 ([i][n], Q*N doubles each),
+ * rebuilt from the stored state. */
+int lb_get_populations(lb_handle *h, double *f1, double *f2);
+
+/* Per-node diagnostics of the current state: psi (N doubles; wall rows hold
+ * the copied value), F_rep (dim*N doubles) and the NCI hit distance h
+ * (N int32, 0 = no hit).  Any pointer may be NULL. */
+int lb_get_nci(lb_handle *h, double *psi, double *frep, int32_t *hit);
+
+void lb_destroy(lb_handle *h);
+
+/* Lattice tables of the library's direction order: c[Q*3] (x,y,z), w[Q].
+ * Returns Q, or LB_EINVAL for an unknown lattice. */
+int lb_lattice_tables(int32_t lattice, int32_t *c, double *w);
+
+/* Step counter of the handle (number of completed lb_step steps). */
+int64_t lb_time(const lb_handle *h);
+
+/* Device bytes held by the handle (state, phase field, scratch). */
+int64_t lb_device_bytes(const lb_handle *h);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around
+ * every k_phase and k_main launch of lb_step (measurement support; adds one
+ * event per launch).  lb_kernel_times synchronises the stream, returns the
+ * summed durations (ms) and launch count since the last call, and resets. */
+int lb_profile(lb_handle *h, int enable);
+int lb_kernel_times(lb_handle *h, double *ms_phase, double *ms_main, int64_t *launches);
+
+/* Achievable-bandwidth reference: a plain streaming copy of `bytes` bytes
+ * (16-byte vector loads/stores) repeated `iters` times on the current device;
+ * returns the average per-copy duration (ms) and the read+write rate (GB/s).
+ * Allocates and frees two device buffers. */
+int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double *gbps);
+
+/* Thread-local message of the last failure ("" if none). */
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

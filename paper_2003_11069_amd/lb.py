@@ -1,0 +1,262 @@
+"""ctypes binding of the HIP C-ABI library ``liblbnci.so`` (include/lbnci.h).
+
+Argument marshalling only: every step of the lattice Boltzmann update runs in
+the library's HIP kernels.  There is no CPU fallback; a missing library or
+GPU raises.  Streams come from PyTorch when it is available (the handle then
+enqueues its work on ``torch.cuda.current_stream()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import sys
+from dataclasses import dataclass, field, asdict
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("LBNCI_LIB", os.path.join(_PKG, "liblbnci.so"))
+
+LB_D2Q9, LB_D3Q27 = 0, 1
+LB_STORE_FP32, LB_STORE_FP16_DEV, LB_STORE_BF16_DEV, LB_STORE_FP32_F32 = 0, 1, 2, 3
+STORAGE = {"fp32": LB_STORE_FP32, "fp16": LB_STORE_FP16_DEV, "bf16": LB_STORE_BF16_DEV,
+           "fp32_f32": LB_STORE_FP32_F32}
+ERRORS = {-1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE", -4: "LB_ENUMERIC", -5: "LB_ESTATE"}
+
+
+class LBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lb_params(C.Structure):
+    _fields_ = [("lattice", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("walls_y", C.c_int32), ("tau", C.c_double), ("A_s", C.c_double),
+                ("beta", C.c_double), ("A_nci", C.c_double), ("h_min", C.c_double),
+                ("h_max", C.c_double), ("force", C.c_double * 3), ("storage", C.c_int32),
+                ("obs_every", C.c_int32), ("conv_window", C.c_int32), ("conv_m", C.c_int32),
+                ("conv_eps", C.c_double)]
+
+
+class lb_obs(C.Structure):
+    _fields_ = [("step", C.c_int64), ("mass", C.c_double * 2), ("mom", C.c_double * 3),
+                ("Q", C.c_double), ("Q_d", C.c_double), ("umax", C.c_double),
+                ("Q_window", C.c_double), ("converged", C.c_int32), ("flags", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads liblbnci.so and declares the C ABI.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P, dp, ip = C.POINTER, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    vp = C.c_void_p
+    sig = {
+        "lb_create": ([P(lb_params), vp, P(vp)], C.c_int),
+        "lb_init_fields": ([vp, dp, dp, dp], C.c_int),
+        "lb_set_populations": ([vp, dp, dp], C.c_int),
+        "lb_step": ([vp, C.c_int64], C.c_int),
+        "lb_observables": ([vp, P(lb_obs)], C.c_int),
+        "lb_get_fields": ([vp, dp, dp, dp], C.c_int),
+        "lb_get_populations": ([vp, dp, dp], C.c_int),
+        "lb_get_nci": ([vp, dp, dp, ip], C.c_int),
+        "lb_destroy": ([vp], None),
+        "lb_lattice_tables": ([C.c_int32, ip, dp], C.c_int),
+        "lb_time": ([vp], C.c_int64),
+        "lb_device_bytes": ([vp], C.c_int64),
+        "lb_last_error": ([], C.c_char_p),
+        "lb_profile": ([vp, C.c_int], C.c_int),
+        "lb_kernel_times": ([vp, dp, dp, P(C.c_int64)], C.c_int),
+        "lb_copy_probe": ([C.c_int64, C.c_int, vp, dp, dp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise LBError(rc, _lib.lb_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def current_stream_handle():
+    """hipStream_t of torch's current stream when the caller already uses
+    torch (torch provides streams only), else 0 = the default stream."""
+    torch = sys.modules.get("torch")
+    if torch is not None:
+        try:
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+    return 0
+
+
+def copy_probe(nbytes: int, iters: int = 20, stream: int | None = None):
+    """Achievable streaming bandwidth (read + write) of a plain copy kernel."""
+    lib = load_library()
+    ms = C.c_double(); gb = C.c_double()
+    st = current_stream_handle() if stream is None else stream
+    _check(lib.lb_copy_probe(int(nbytes), int(iters), C.c_void_p(st), C.byref(ms), C.byref(gb)))
+    return {"ms": ms.value, "GBps": gb.value}
+
+
+def lattice_tables(lattice: int):
+    lib = load_library()
+    c = np.zeros((27, 3), np.int32)
+    w = np.zeros(27)
+    Q = _check(lib.lb_lattice_tables(lattice, _ip(c), _dp(w)))
+    return c[:Q].copy(), w[:Q].copy()
+
+
+@dataclass
+class Params:
+    """Mirror of ``lb_params``."""
+    lattice: int = LB_D2Q9
+    nx: int = 128
+    ny: int = 64
+    nz: int = 1
+    walls_y: int = 0
+    tau: float = 1.0
+    A_s: float = 0.05
+    beta: float = 0.7
+    A_nci: float = 0.005
+    h_min: float = 2.0
+    h_max: float = 4.0
+    force: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    storage: int = LB_STORE_FP32
+    obs_every: int = 0
+    conv_window: int = 0
+    conv_m: int = 3
+    conv_eps: float = 1e-4
+
+    @classmethod
+    def from_dict(cls, d: dict, **kw):
+        keys = {f for f in cls.__dataclass_fields__}
+        v = {k: d[k] for k in d if k in keys}
+        v.update(kw)
+        return cls(**v)
+
+    def to_c(self) -> lb_params:
+        p = lb_params()
+        for k, v in asdict(self).items():
+            if k == "force":
+                for a in range(3):
+                    p.force[a] = float(v[a]) if a < len(v) else 0.0
+            else:
+                setattr(p, k, v)
+        return p
+
+    @property
+    def dim(self):
+        return 2 if self.lattice == LB_D2Q9 else 3
+
+    @property
+    def N(self):
+        return self.nx * self.ny * self.nz
+
+
+class Lattice:
+    """One lattice handle (lb_create ... lb_destroy)."""
+
+    def __init__(self, p: Params, stream: int | None = None):
+        self.lib = load_library()
+        self.p = p
+        self._pc = p.to_c()
+        h = C.c_void_p()
+        st = current_stream_handle() if stream is None else stream
+        _check(self.lib.lb_create(C.byref(self._pc), C.c_void_p(st), C.byref(h)))
+        self.h = h
+        self.c, self.w = lattice_tables(p.lattice)
+        self.Q = len(self.w)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def N(self):
+        return self.p.N
+
+    @property
+    def t(self) -> int:
+        return self.lib.lb_time(self.h)
+
+    @property
+    def device_bytes(self) -> int:
+        return self.lib.lb_device_bytes(self.h)
+
+    def init_fields(self, rho1, rho2, u=None):
+        r1 = np.ascontiguousarray(rho1, np.float64).ravel()
+        r2 = np.ascontiguousarray(rho2, np.float64).ravel()
+        if r1.size != self.N or r2.size != self.N:
+            raise ValueError("density arrays must hold N values")
+        uu = None
+        if u is not None:
+            uu = np.ascontiguousarray(u, np.float64).ravel()
+            if uu.size != self.p.dim * self.N:
+                raise ValueError("u must hold dim*N values")
+        _check(self.lib.lb_init_fields(self.h, _dp(r1), _dp(r2), _dp(uu)))
+
+    def set_populations(self, f1, f2):
+        a = np.ascontiguousarray(f1, np.float64).reshape(self.Q, self.N)
+        b = np.ascontiguousarray(f2, np.float64).reshape(self.Q, self.N)
+        _check(self.lib.lb_set_populations(self.h, _dp(a), _dp(b)))
+
+    def step(self, n: int = 1):
+        _check(self.lib.lb_step(self.h, int(n)))
+
+    def observables(self) -> dict:
+        o = lb_obs()
+        rc = self.lib.lb_observables(self.h, C.byref(o))
+        if rc < 0 and rc != -4:
+            _check(rc)
+        return {"step": o.step, "mass": np.array(o.mass[:]), "mom": np.array(o.mom[:]), "Q": o.Q,
+                "Q_d": o.Q_d, "umax": o.umax, "Q_window": o.Q_window,
+                "converged": bool(o.converged), "flags": o.flags, "rc": rc}
+
+    def fields(self):
+        r1 = np.zeros(self.N); r2 = np.zeros(self.N); u = np.zeros(self.p.dim * self.N)
+        _check(self.lib.lb_get_fields(self.h, _dp(r1), _dp(r2), _dp(u)))
+        return r1, r2, u.reshape(self.p.dim, self.N)
+
+    def populations(self):
+        f1 = np.zeros((self.Q, self.N)); f2 = np.zeros((self.Q, self.N))
+        _check(self.lib.lb_get_populations(self.h, _dp(f1), _dp(f2)))
+        return f1, f2
+
+    def profile(self, enable: bool = True):
+        _check(self.lib.lb_profile(self.h, int(enable)))
+
+    def kernel_times(self):
+        a = C.c_double(); b = C.c_double(); n = C.c_int64()
+        _check(self.lib.lb_kernel_times(self.h, C.byref(a), C.byref(b), C.byref(n)))
+        return {"ms_phase": a.value, "ms_main": b.value, "launches": n.value}
+
+    def nci(self):
+        psi = np.zeros(self.N); fr = np.zeros(self.p.dim * self.N); hit = np.zeros(self.N, np.int32)
+        _check(self.lib.lb_get_nci(self.h, _dp(psi), _dp(fr), _ip(hit)))
+        return psi, fr.reshape(self.p.dim, self.N), hit
