@@ -34,14 +34,15 @@ B_ALG_TWO_POP = {2: 2 * 2 * 9 * 4 + 8, 3: 2 * 2 * 27 * 4 + 8}
 
 def main_kernel_bytes(dim: int, storage: str) -> int:
     """Compulsory HBM bytes per fluid node of one k_main launch in the
-    library's layout: state read once (s_i, a, B) + state written once + psi
-    read once."""
+    library's layout: the Q stored deviations s_i read once, rho1 and psi read
+    once, the full state (s_i, colour fraction a, colour vector B) written
+    once."""
     Q = 9 if dim == 2 else 27
     s_b = 2 if storage in ("fp16", "bf16") else 4
     r_b = 8 if storage == "fp32" else 4
-    rest_extra = 4 if storage in ("fp16", "bf16") else 0  # FP32 rest slot
-    state = Q * s_b + rest_extra + r_b + 4 * dim
-    return 2 * state + r_b
+    rest_extra = 4 - s_b if storage in ("fp16", "bf16") else 0  # FP32 rest slot
+    pops = Q * s_b + rest_extra
+    return (pops + 2 * r_b) + (pops + r_b + 4 * dim)
 
 
 def kernel_source_hash() -> str:

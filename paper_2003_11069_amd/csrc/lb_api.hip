@@ -257,6 +257,12 @@ int validate(const lb_params *p) {
     if (!std::isfinite(p->force[d])) return fail(LB_EINVAL, "force must be finite");
   if (p->storage < LB_STORE_FP32 || p->storage > LB_STORE_FP32_F32)
     return fail(LB_EINVAL, "unknown storage %d", p->storage);
+  {  // the stored deviations of all directions are addressed with 32-bit byte offsets
+    const uint64_t Q = p->lattice == LB_D2Q9 ? 9 : 27;
+    const uint64_t sb = (p->storage == LB_STORE_FP16_DEV || p->storage == LB_STORE_BF16_DEV) ? 2 : 4;
+    if (Q * sb * (uint64_t)p->nx * p->ny * p->nz >= ((uint64_t)1 << 32))
+      return fail(LB_EINVAL, "lattice too large: Q*N*element size must stay below 4 GiB");
+  }
   if (p->obs_every < 0 || p->conv_window < 0 || p->conv_m < 0 || !(p->conv_eps >= 0))
     return fail(LB_EINVAL, "bad observable/convergence settings");
   return LB_OK;
@@ -587,7 +593,13 @@ int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   const int threads = 256;
-  const int blocks = (int)std::min<int64_t>((n4 + threads - 1) / threads, 256 * 64);
+  const int64_t nblk = (n4 + threads - 1) / threads;
+  if (nblk > INT32_MAX) {
+    (void)hipFree(src);
+    (void)hipFree(dst);
+    return fail(LB_EINVAL, "copy probe too large");
+  }
+  const int blocks = (int)nblk;
   hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(threads), 0, st, src, dst, n4, 1);
   hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(threads), 0, st, dst, src, n4, 0);
   (void)hipEventRecord(e0, st);

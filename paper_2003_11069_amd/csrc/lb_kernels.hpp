@@ -161,6 +161,43 @@ __device__ __forceinline__ Wrap make_wrap(int nx, int ny, int nz, int walls, int
   return w;
 }
 
+// Byte offsets (relative to node n) of the source x - c along each axis, for
+// c = -1, 0, +1, scaled by the element size; the stored deviations of all
+// directions share one base pointer (direction stride N elements).
+struct Offs {
+  uint32_t x[3], y[3], z[3];
+};
+
+template <int D, uint32_t SB>
+__device__ __forceinline__ Offs make_offs(int nx, int ny, int nz, int walls, int x, int y, int z) {
+  Offs o;
+  const uint32_t sy = (uint32_t)nx, sz = (uint32_t)nx * (uint32_t)ny;
+  o.x[0] = (x == nx - 1 ? 0u - (uint32_t)(nx - 1) : 1u) * SB;  // c = -1: source x+1
+  o.x[1] = 0u;
+  o.x[2] = (x == 0 ? (uint32_t)(nx - 1) : 0u - 1u) * SB;       // c = +1: source x-1
+  o.y[0] = (!walls && y == ny - 1 ? 0u - (uint32_t)(ny - 1) * sy : sy) * SB;
+  o.y[1] = 0u;
+  o.y[2] = (!walls && y == 0 ? (uint32_t)(ny - 1) * sy : 0u - sy) * SB;
+  if (D == 3) {
+    o.z[0] = (z == nz - 1 ? 0u - (uint32_t)(nz - 1) * sz : sz) * SB;
+    o.z[2] = (z == 0 ? (uint32_t)(nz - 1) * sz : 0u - sz) * SB;
+  } else {
+    o.z[0] = 0u;
+    o.z[2] = 0u;
+  }
+  o.z[1] = 0u;
+  return o;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldb(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (size_t)byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void stb(T *base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (size_t)byte_off) = v;
+}
+
 template <int D>
 __device__ __forceinline__ uint32_t source(const Wrap &w, uint32_t n, int cx, int cy, int cz) {
   uint32_t s = n;
@@ -186,9 +223,12 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
                                      const R *ta, const float *tB, int lidx, float *f, R *c1out,
                                      R &dr, R &r1, R *j) {
   using L = Lat<D>;
+  constexpr uint32_t SB = sizeof(S);
   dr = 0; r1 = 0;
   j[0] = j[1] = j[2] = 0;
   const Wrap wr = make_wrap(A.nx, A.ny, A.nz, A.walls, x, y, z);
+  const Offs of = make_offs<D, SB>(A.nx, A.ny, A.nz, A.walls, x, y, z);
+  const uint32_t nb = n * SB, NB = A.N * SB;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
@@ -199,15 +239,14 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
       sv = (float)A.xt[(size_t)i * A.N + n];
       if (COL != COL_NONE) c1 = (R)A.xc[(size_t)i * A.N + n];
     } else {
-      const uint32_t src = source<D>(wr, n, cx, cy, cz);
       if (!is_fp32<S>::value && i == L::REST) sv = ld(A.in.s0, n);
-      else sv = to_f(ld(A.in.s + (size_t)i * A.N, src));
+      else sv = to_f(ldb(A.in.s, nb + of.x[cx + 1] + of.y[cy + 1] + of.z[cz + 1] + (uint32_t)i * NB));
       if (COL != COL_NONE) {
         const bool bb = A.walls && cy != 0 && (y - cy == 0 || y - cy == A.ny - 1);
         const R sgn = bb ? (R)-1 : (R)1;
         R av, Bx = 0, By = 0, Bz = 0;
         if (COL == COL_GLOBAL) {
-          const uint32_t cs = bb ? n : src;
+          const uint32_t cs = bb ? n : source<D>(wr, n, cx, cy, cz);
           av = ld(A.in.a, cs);
           if (cx) Bx = (R)ld(A.in.B, cs);
           if (cy) By = (R)ld(A.in.B + A.N, cs);
@@ -462,42 +501,53 @@ __global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) 
       const float drf = (float)dr, rhof = (float)rho;
       const float Ghf[3] = {(float)Gh[0], (float)Gh[1], (float)Gh[2]};
       const bool low = A.walls && y == 1, high = A.walls && y == A.ny - 2;
-      // Store as computed.  The rest slot absorbs the rounding of the other
-      // directions (node mass closure); a is taken against the density of the
-      // rounded populations so that the component-1 mass is carried exactly.
-      float err = 0.f, sn_rest = 0.f;
-      R dr_t = 0;
+      // Directions i and opp(i) share the even part of the update and negate
+      // the odd part:  sn = (1-om) f + C +- O  with
+      //   C = om dr + rho (AF + (om-1) A) + pg (cG^2 - 1/3),
+      //   O = 3 rho (cuF + (om-1) cu),  A = 4.5 cu^2 - 1.5 u.u (likewise AF).
+      // The rest slot is set from the pre-collision density deviation dr (R)
+      // minus the stored other directions, so each node keeps its mass up to
+      // one rounding of the rest slot (the collision conserves mass exactly;
+      // this removes the FP32 update's and the storage's rounding of it).  a
+      // is taken against the density of the stored populations so that the
+      // component-1 mass is carried exactly.
+      const float om = tinv, omc = 1.f - om, om1 = om - 1.f;
+      const float cdr = om * drf - pg * (1.0f / 3.0f);
+      const uint32_t nb = n * (uint32_t)sizeof(S), NB = A.N * (uint32_t)sizeof(S);
+      R sum_q = 0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
+      for (int i = 0; i < L::REST; ++i) {
+        const int io = L::opp(i);
         const int icx = L::cx(i), icy = L::cy(i), icz = L::cz(i);
-        const float cx = (float)icx, cy = (float)icy, cz = (float)icz;
-        const float cu = cx * uf[0] + cy * uf[1] + cz * uf[2];
-        const float cuF = cx * uFf[0] + cy * uFf[1] + cz * uFf[2];
-        const float P = 3.f * cu + 4.5f * cu * cu - 1.5f * uu;
-        const float PF = 3.f * cuF + 4.5f * cuF * cuF - 1.5f * uuF;
-        const float cG = cx * Ghf[0] + cy * Ghf[1] + cz * Ghf[2];
-        const float fi = f[i];
-        const float sn = fi - (fi - drf - rhof * P) * tinv + rhof * (PF - P) +
-                         pg * (cG * cG - (1.0f / 3.0f));
-        if (i == L::REST) { sn_rest = sn; continue; }
-        const S q = from_f<S>(sn);
-        st(A.out.s + (size_t)i * A.N, n, q);
-        // population heading into a wall: reflected copy into the wall row
-        if ((icy == -1 && low) || (icy == 1 && high)) {
-          const int xw = wrapi(x + icx, A.nx);
-          const int zw = (D == 3) ? wrapi(z + icz, A.nz) : 0;
+        const float cu = (float)icx * uf[0] + (float)icy * uf[1] + (float)icz * uf[2];
+        const float cuF = (float)icx * uFf[0] + (float)icy * uFf[1] + (float)icz * uFf[2];
+        const float cG = (float)icx * Ghf[0] + (float)icy * Ghf[1] + (float)icz * Ghf[2];
+        const float Ae = 4.5f * cu * cu - 1.5f * uu;
+        const float AF = 4.5f * cuF * cuF - 1.5f * uuF;
+        const float C = cdr + rhof * (AF + om1 * Ae) + pg * (cG * cG);
+        const float O = 3.f * rhof * (cuF + om1 * cu);
+        const float sn_i = omc * f[i] + C + O;
+        const float sn_o = omc * f[io] + C - O;
+        const S q_i = from_f<S>(sn_i), q_o = from_f<S>(sn_o);
+        stb(A.out.s, nb + (uint32_t)i * NB, q_i);
+        stb(A.out.s, nb + (uint32_t)io * NB, q_o);
+        // populations heading into a wall: reflected copy into the wall row,
+        // node x + c_d, slot opp(d) (direction i has c_y = icy, opp(i) -icy)
+        auto ghost = [&](int d, int dcx, int dcy, int dcz, S q) {
+          const int xw = wrapi(x + dcx, A.nx);
+          const int zw = (D == 3) ? wrapi(z + dcz, A.nz) : 0;
           const uint32_t nw =
-              (uint32_t)xw + (uint32_t)A.nx * ((uint32_t)(y + icy) + (uint32_t)A.ny * zw);
-          st(A.out.s + (size_t)L::opp(i) * A.N, nw, q);
-        }
-        const float qf = to_f(q);
-        if (!is_fp32<S>::value) err += (float)L::w(i) * (sn - qf);
-        dr_t += (R)L::w(i) * (R)qf;
+              (uint32_t)xw + (uint32_t)A.nx * ((uint32_t)(y + dcy) + (uint32_t)A.ny * zw);
+          stb(A.out.s, nw * (uint32_t)sizeof(S) + (uint32_t)L::opp(d) * NB, q);
+        };
+        if ((icy == -1 && low) || (icy == 1 && high)) ghost(i, icx, icy, icz, q_i);
+        if ((icy == 1 && low) || (icy == -1 && high)) ghost(io, -icx, -icy, -icz, q_o);
+        sum_q += (R)L::w(i) * ((R)to_f(q_i) + (R)to_f(q_o));
       }
-      const float srest = sn_rest + err * (float)(1.0 / L::w(L::REST));
-      if (is_fp32<S>::value) st(A.out.s + (size_t)L::REST * A.N, n, from_f<S>(srest));
+      const float srest = (float)((dr - sum_q) * (R)(1.0 / L::w(L::REST)));
+      if (is_fp32<S>::value) stb(A.out.s, nb + (uint32_t)L::REST * NB, from_f<S>(srest));
       else st(A.out.s0, n, srest);
-      dr_t += (R)L::w(L::REST) * (R)srest;
+      const R dr_t = sum_q + (R)L::w(L::REST) * (R)srest;
       st(A.out.a, n, r1 / ((R)1 + dr_t));
       const R b = A.beta * r1 * (rho - r1) * irho;
       st(A.out.B, n, (float)(b * Gh[0]));
@@ -592,24 +642,25 @@ __global__ __launch_bounds__(256) void k_obs_reduce(const double *partials, int 
   }
 }
 
-// Streaming copy (16-byte accesses, grid-stride, 4 independent vectors in
-// flight per thread) used as the achievable bandwidth reference; init != 0
-// fills the source instead.
+// Streaming copy used as the achievable-bandwidth reference: one 16-byte
+// vector per thread, non-temporal loads and stores (the fastest plain copy
+// pattern measured on MI355X); init != 0 fills the source instead.
 __global__ __launch_bounds__(256) void k_copy_probe(float4 *src, float4 *dst, int64_t n4, int init) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n4) return;
   if (init) {
-    for (; k < n4; k += stride) src[k] = make_float4((float)k, 1.f, 2.f, 3.f);
+    src[k] = make_float4((float)k, 1.f, 2.f, 3.f);
     return;
   }
-  for (; k + 3 * stride < n4; k += 4 * stride) {
-    const float4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
-    dst[k] = a;
-    dst[k + stride] = b;
-    dst[k + 2 * stride] = c;
-    dst[k + 3 * stride] = d;
-  }
-  for (; k < n4; k += stride) dst[k] = src[k];
+  float4 v;
+  v.x = __builtin_nontemporal_load(&src[k].x);
+  v.y = __builtin_nontemporal_load(&src[k].y);
+  v.z = __builtin_nontemporal_load(&src[k].z);
+  v.w = __builtin_nontemporal_load(&src[k].w);
+  __builtin_nontemporal_store(v.x, &dst[k].x);
+  __builtin_nontemporal_store(v.y, &dst[k].y);
+  __builtin_nontemporal_store(v.z, &dst[k].z);
+  __builtin_nontemporal_store(v.w, &dst[k].w);
 }
 
 }  // namespace lbk
