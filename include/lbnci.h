@@ -165,6 +165,42 @@ int lb_kernel_times(lb_handle *h, double *ms_phase, double *ms_main, int64_t *la
  * Allocates and frees two device buffers. */
 int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double *gbps);
 
+/* ---- Batched stepping of many independent lattices ("channels") --------
+ * For sweeps of the kind the paper runs over pressure gradient and NCI
+ * strength (Results: flow rate versus driving), many small lattices of
+ * uneven size are stepped together on one GPU.  All channels of a batch share
+ * lattice type, storage and obs_every; sizes and physical parameters differ.
+ * Channels with conv_window > 0 retire (stop stepping) once their windowed
+ * flow-rate test is satisfied. */
+typedef struct lb_batch lb_batch;
+#define LB_BATCH_LAUNCH 0     /* per step: phase, main and bookkeeping launches over a
+                                 tile table of all channels, replayed from a hipGraph */
+#define LB_BATCH_PERSISTENT 1 /* one cooperative persistent launch for all steps; each
+                                 channel synchronises only its own group of blocks */
+
+/* p: n parameter sets.  Creates n handles on the stream plus the tile tables
+ * and persistent-launch groups.  Errors as lb_create, and LB_EINVAL when the
+ * channels differ in lattice/storage/obs_every. */
+int lb_batch_create(const lb_params *p, int32_t n, void *hip_stream, lb_batch **out);
+/* As lb_init_fields for channel c (0 <= c < n). */
+int lb_batch_init_fields(lb_batch *b, int32_t c, const double *rho1, const double *rho2,
+                         const double *u);
+/* Advances every active channel by n steps (synchronises the stream at the
+ * end).  The first call after initialisation performs the explicit first step
+ * of every channel as one plain step (channels must be initialised together).
+ * Errors: LB_ESTATE (uninitialised channel), LB_EDEVICE (launch failure or a
+ * channel barrier that did not complete within its spin limit). */
+int lb_batch_step(lb_batch *b, int64_t n, int32_t mode);
+int lb_batch_observables(lb_batch *b, int32_t c, lb_obs *out);
+int lb_batch_get_fields(lb_batch *b, int32_t c, double *rho1, double *rho2, double *u);
+/* Steps completed by channel c, whether it is still active, and the number of
+ * blocks of its persistent group. */
+int lb_batch_info(lb_batch *b, int32_t c, int64_t *steps, int32_t *active, int32_t *blocks);
+/* 1 while both modes run from hipGraphs, 0 after a graph path failed and
+ * direct launches are used. */
+int lb_batch_graphs(lb_batch *b);
+void lb_batch_destroy(lb_batch *b);
+
 /* Thread-local message of the last failure ("" if none). */
 const char *lb_last_error(void);
 

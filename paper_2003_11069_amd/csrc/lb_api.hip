@@ -1,7 +1,6 @@
 // lb_api.hip -- C ABI of the colour-gradient + NCI lattice Boltzmann library
 // (declarations and argument contracts in include/lbnci.h).
-#include "lbnci.h"
-#include "lb_kernels.hpp"
+#include "lb_internal.hpp"
 
 #include <hip/hip_runtime.h>
 #include <cmath>
@@ -13,9 +12,9 @@
 #include <vector>
 
 using namespace lbk;
+using namespace lbi;
 
-namespace {
-
+namespace lbi {
 thread_local std::string g_err;
 
 int fail(int code, const char *fmt, ...) {
@@ -27,79 +26,9 @@ int fail(int code, const char *fmt, ...) {
   g_err = buf;
   return code;
 }
+}  // namespace lbi
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess) return fail(LB_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-// Tile shapes (x extent is always one 64-wide wavefront); the defaults can be
-// overridden at build time for tile sweeps.
-#ifndef LBNCI_XCD_REMAP
-#define LBNCI_XCD_REMAP 1
-#endif
-#ifndef LBNCI_BY2
-#define LBNCI_BY2 4
-#endif
-#ifndef LBNCI_BY3
-#define LBNCI_BY3 4
-#endif
-#ifndef LBNCI_TZ3
-#define LBNCI_TZ3 4
-#endif
-#ifndef LBNCI_H3
-#define LBNCI_H3 1
-#endif
-#ifndef LBNCI_TZP3
-#define LBNCI_TZP3 2
-#endif
-#ifndef LBNCI_WPE_MAIN3
-#define LBNCI_WPE_MAIN3 1
-#endif
-#ifndef LBNCI_WPE_PHASE3
-#define LBNCI_WPE_PHASE3 1
-#endif
-constexpr int BY2 = LBNCI_BY2, TZ2 = 1, H2 = 4;  // D2Q9: halo 4, NCI probe from LDS only
-constexpr int BY3 = LBNCI_BY3, TZ3 = LBNCI_TZ3, H3 = LBNCI_H3;  // D3Q27: probe beyond the halo from L2
-constexpr int TZP3 = LBNCI_TZP3;                 // k_phase z-planes per block (3-D)
-
-}  // namespace
-
-struct lb_handle {
-  lb_params p;
-  int D, Q;
-  int64_t N;
-  hipStream_t stream;
-  int store;         // lb_storage
-  size_t s_elem;     // bytes per stored s value
-  size_t r_elem;     // bytes per compute-type value (a, psi)
-  // state, two copies
-  void *s[2] = {nullptr, nullptr};
-  float *s0[2] = {nullptr, nullptr};
-  void *a[2] = {nullptr, nullptr};
-  float *B[2] = {nullptr, nullptr};
-  void *psi = nullptr;
-  void *r1 = nullptr;
-  double *xt = nullptr, *xc = nullptr;  // explicit first-step state
-  double *partials = nullptr;
-  int nparts = 0;
-  ObsDev *obs = nullptr;
-  int cur = 0;
-  int initialised = 0;
-  int explicit_src = 0;
-  int64_t t = 0;
-  int xcd_remap = LBNCI_XCD_REMAP;
-  int64_t bytes = 0;
-  // per-kernel event timing
-  int profile = 0;
-  std::vector<hipEvent_t> ev;  // triples: before phase, between, after main
-  // lattice tables (host)
-  int c[27][3];
-  double w[27];
-};
-
-namespace {
+namespace lbi {
 
 template <int D>
 void fill_tables(lb_handle *h) {
@@ -124,30 +53,6 @@ int blocks_phase(const lb_handle *h) {
   return ((p.nx + 63) / 64) * ((p.ny + 3) / 4) * gz;
 }
 
-template <typename S, typename R>
-Args<S, R> make_args(lb_handle *h, int in, int out) {
-  Args<S, R> a{};
-  const lb_params &p = h->p;
-  a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.walls = p.walls_y;
-  a.N = (uint32_t)h->N;
-  a.tau_inv = (R)(1.0 / p.tau);
-  a.half_As = (R)(0.5 * p.A_s);
-  a.beta = (R)p.beta;
-  a.A = (R)p.A_nci;
-  a.h_min = (R)p.h_min;
-  a.h_max = (R)p.h_max;
-  for (int d = 0; d < 3; ++d) a.F[d] = (R)p.force[d];
-  a.smax = (int)std::floor(p.h_max);
-  a.in = State<S, R>{(S *)h->s[in], h->s0[in], (R *)h->a[in], h->B[in]};
-  a.out = State<S, R>{(S *)h->s[out], h->s0[out], (R *)h->a[out], h->B[out]};
-  a.xt = h->xt;
-  a.xc = h->xc;
-  a.psi = (R *)h->psi;
-  a.r1 = (R *)h->r1;
-  a.partials = h->partials;
-  a.xcd_remap = h->xcd_remap;
-  return a;
-}
 
 template <int D, typename S, typename R, int SRC, int MODE>
 void launch_main(lb_handle *h, const Args<S, R> &a) {
@@ -213,8 +118,7 @@ int run_pass(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t
   return LB_OK;
 }
 
-int dispatch(lb_handle *h, int mode, double *o0 = nullptr, double *o1 = nullptr,
-             double *o2 = nullptr, int32_t *io = nullptr) {
+int dispatch(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t *io) {
   const bool d2 = h->D == 2;
   switch (h->store) {
     case LB_STORE_FP32:
@@ -623,6 +527,6 @@ int64_t lb_time(const lb_handle *h) { return h ? h->t : -1; }
 
 int64_t lb_device_bytes(const lb_handle *h) { return h ? h->bytes : -1; }
 
-const char *lb_last_error(void) { return g_err.c_str(); }
+const char *lb_last_error(void) { return lbi::g_err.c_str(); }
 
 }  // extern "C"

@@ -276,23 +276,26 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
 }
 
 // ---------------------------------------------------------------------------
-// k_phase: rho1 and psi(x,t) = (rho1 - rho2)/rho at every fluid node.  Block
-// (64, 4) threads over a 64 x 4 x TZP tile; the sources' colour scalars are
-// staged in LDS with a one-node halo (each is read by up to Q neighbours).
-template <int D, typename S, typename R, int SRC, int TZP, int WPE = 1>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_phase(Args<S, R> A) {
-  constexpr int PX = 66, PY = 6, PZ = (D == 3) ? TZP + 2 : 1;
-  constexpr int TS = PX * PY * PZ;
-  constexpr bool STAGE = (SRC == PULL);
-  __shared__ R ta[STAGE ? TS : 1];
-  __shared__ float tB[STAGE ? D * TS : 1];
-  const int gx = (A.nx + 63) / 64;
-  const int gy = (A.ny + 3) / 4;
-  const int lb = logical_block(blockIdx.x, gridDim.x, A.xcd_remap);
-  const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
+// Phase pass over one 64 x 4 x TZP tile (block of 64 x 4 threads): rho1 and
+// psi(x,t) = (rho1 - rho2)/rho at every fluid node.  The sources' colour
+// scalars are staged in LDS with a one-node halo (each is read by up to Q
+// neighbours).  Safe to call repeatedly from one block (persistent kernels):
+// it synchronises before reusing the LDS tile and never returns early.
+template <int D, int TZP>
+struct PhaseTile {
+  static constexpr int PX = 66, PY = 6, PZ = (D == 3) ? TZP + 2 : 1;
+  static constexpr int TS = PX * PY * PZ;
+};
+
+template <int D, typename S, typename R, int SRC, int TZP>
+__device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, int bz, R *ta,
+                                           float *tB) {
+  constexpr int PX = PhaseTile<D, TZP>::PX, PY = PhaseTile<D, TZP>::PY;
+  constexpr int TS = PhaseTile<D, TZP>::TS;
   const int x0 = bx * 64, y0 = by * 4, z0 = (D == 3) ? bz * TZP : 0;
   const int tid = threadIdx.x + 64 * threadIdx.y;
-  if (STAGE) {
+  if (SRC == PULL) {
+    __syncthreads();
     for (int k = tid; k < TS; k += 256) {
       const int lx = k % PX, ly = (k / PX) % PY, lz = k / (PX * PY);
       const int gxx = wrapi(x0 + lx - 1, A.nx);
@@ -307,20 +310,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __syncthreads();
   }
   const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-  if (x >= A.nx || y >= A.ny) return;
-  if (A.walls && (y == 0 || y == A.ny - 1)) return;
-  for (int tz = 0; tz < ((D == 3) ? TZP : 1); ++tz) {
-    const int z = z0 + tz;
-    if (z >= A.nz) break;
-    const uint32_t n = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
-    const int lidx = (threadIdx.x + 1) + PX * ((threadIdx.y + 1) + PY * ((D == 3) ? tz + 1 : 0));
-    float f[Lat<D>::Q];
-    R dr, r1, j[3];
-    pull<D, S, R, SRC, COL_LDS, false, PX, PY, TS>(A, x, y, z, n, ta, tB, lidx, f, nullptr, dr, r1, j);
-    const R rho = (R)1 + dr;
-    st(A.psi, n, ((R)2 * r1 - rho) / rho);
-    st(A.r1, n, r1);
+  if (x < A.nx && y < A.ny && !(A.walls && (y == 0 || y == A.ny - 1))) {
+    for (int tz = 0; tz < ((D == 3) ? TZP : 1); ++tz) {
+      const int z = z0 + tz;
+      if (z >= A.nz) break;
+      const uint32_t n = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
+      const int lidx = (threadIdx.x + 1) + PX * ((threadIdx.y + 1) + PY * ((D == 3) ? tz + 1 : 0));
+      float f[Lat<D>::Q];
+      R dr, r1, j[3];
+      pull<D, S, R, SRC, COL_LDS, false, PX, PY, TS>(A, x, y, z, n, ta, tB, lidx, f, nullptr, dr, r1, j);
+      const R rho = (R)1 + dr;
+      st(A.psi, n, ((R)2 * r1 - rho) / rho);
+      st(A.r1, n, r1);
+    }
   }
+}
+
+// Number of phase tiles of a lattice.
+template <int D, int TZP>
+__host__ __device__ __forceinline__ int phase_tiles(int nx, int ny, int nz) {
+  return ((nx + 63) / 64) * ((ny + 3) / 4) * ((D == 3) ? (nz + TZP - 1) / TZP : 1);
+}
+
+template <int D, int TZP>
+__device__ __forceinline__ void phase_decode(int nx, int ny, int lb, int &bx, int &by, int &bz) {
+  const int gx = (nx + 63) / 64, gy = (ny + 3) / 4;
+  bx = lb % gx;
+  by = (lb / gx) % gy;
+  bz = lb / (gx * gy);
+}
+
+// k_phase: one phase tile per block over a single lattice.
+template <int D, typename S, typename R, int SRC, int TZP, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_phase(Args<S, R> A) {
+  constexpr int TS = PhaseTile<D, TZP>::TS;
+  constexpr bool STAGE = (SRC == PULL);
+  __shared__ R ta[STAGE ? TS : 1];
+  __shared__ float tB[STAGE ? D * TS : 1];
+  int bx, by, bz;
+  phase_decode<D, TZP>(A.nx, A.ny, logical_block(blockIdx.x, gridDim.x, A.xcd_remap), bx, by, bz);
+  phase_tile<D, S, R, SRC, TZP>(A, bx, by, bz, ta, tB);
 }
 
 // A_h: A below h_min, A (h_min/h)^3 up to h_max, 0 beyond (Eq. near_c text).
@@ -339,27 +368,44 @@ __device__ __forceinline__ double round_away(double v) { return round(v); }
 __device__ __forceinline__ float round_away(float v) { return roundf(v); }
 
 // ---------------------------------------------------------------------------
-// k_main: block (64, BY) threads, tile 64 x BY x TZ nodes (TZ z-planes per
-// thread in 3-D), psi staged in LDS with a halo of H nodes.  With H = 4 the
-// NCI probe reads only LDS; with a smaller halo the probe falls back to the
-// global psi array for targets outside the halo.
-template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int WPE = 1>
-__global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void k_main(Args<S, R> A) {
+// Main pass over one 64 x BY x TZ tile (block of 64 x BY threads, TZ z-planes
+// per thread in 3-D): psi staged in LDS with a halo of H nodes (with H = 4 the
+// NCI probe reads only LDS; with a smaller halo it falls back to the global
+// psi array beyond the halo), gradient, NCI, pull, collision and store (or the
+// MODE's alternative output).  Observable partials go to partials[slot].  Safe
+// to call repeatedly from one block; it never returns early.
+template <int D, int BY, int TZ, int H>
+struct MainTile {
+  static constexpr int LX = 64 + 2 * H, LY = BY + 2 * H, LZ = (D == 3) ? TZ + 2 * H : 1;
+  static constexpr int TS = LX * LY * LZ;
+};
+
+template <int D, int BY, int TZ>
+__host__ __device__ __forceinline__ int main_tiles(int nx, int ny, int nz) {
+  return ((nx + 63) / 64) * ((ny + BY - 1) / BY) * ((D == 3) ? (nz + TZ - 1) / TZ : 1);
+}
+
+template <int D, int BY>
+__device__ __forceinline__ void main_decode(int nx, int ny, int lb, int &bx, int &by, int &bz) {
+  const int gx = (nx + 63) / 64, gy = (ny + BY - 1) / BY;
+  bx = lb % gx;
+  by = (lb / gx) % gy;
+  bz = lb / (gx * gy);
+}
+
+template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H>
+__device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, int bz, int slot,
+                                          R *tile, double (*red)[8]) {
   using L = Lat<D>;
   constexpr int Q = L::Q;
-  constexpr int LX = 64 + 2 * H, LY = BY + 2 * H, LZ = (D == 3) ? TZ + 2 * H : 1;
+  constexpr int LX = MainTile<D, BY, TZ, H>::LX, LY = MainTile<D, BY, TZ, H>::LY;
+  constexpr int LZ = MainTile<D, BY, TZ, H>::LZ;
   constexpr int NT = 64 * BY;
-  __shared__ R tile[LX * LY * LZ];
-  __shared__ double red[NT / 64][8];
-
-  const int gx = (A.nx + 63) / 64;
-  const int gy = (A.ny + BY - 1) / BY;
-  const int lb = logical_block(blockIdx.x, gridDim.x, A.xcd_remap);
-  const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
   const int x0 = bx * 64, y0 = by * BY, z0 = (D == 3) ? bz * TZ : 0;
   const int tid = threadIdx.x + 64 * threadIdx.y;
 
   // stage psi(tile + halo); wall rows read their fluid neighbour (copy rule)
+  __syncthreads();
   for (int k = tid; k < LX * LY * LZ; k += NT) {
     const int lx = k % LX, ly = (k / LX) % LY, lz = k / (LX * LY);
     const int gxx = wrapi(x0 + lx - H, A.nx);
@@ -574,10 +620,21 @@ __global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) 
     if (tid < 8) {
       double v = red[0][tid];
       for (int wv = 1; wv < NT / 64; ++wv) v = (tid == 7) ? fmax(v, red[wv][tid]) : v + red[wv][tid];
-      A.partials[(size_t)blockIdx.x * 8 + tid] = v;
+      A.partials[(size_t)slot * 8 + tid] = v;
     }
   }
 }
+
+// k_main: one main tile per block over a single lattice.
+template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int WPE = 1>
+__global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void k_main(Args<S, R> A) {
+  __shared__ R tile[MainTile<D, BY, TZ, H>::TS];
+  __shared__ double red[BY][8];
+  int bx, by, bz;
+  main_decode<D, BY>(A.nx, A.ny, logical_block(blockIdx.x, gridDim.x, A.xcd_remap), bx, by, bz);
+  main_tile<D, S, R, SRC, MODE, BY, TZ, H>(A, bx, by, bz, blockIdx.x, tile, red);
+}
+
 
 // ---------------------------------------------------------------------------
 // Observables: deterministic reduction of the per-block partials (fixed
@@ -598,15 +655,17 @@ struct ObsDev {
   int32_t pad;
 };
 
-__global__ __launch_bounds__(256) void k_obs_reduce(const double *partials, int nparts,
-                                                    ObsDev *o, double inv_nx, int W, int m,
-                                                    double eps, int record) {
-  __shared__ double sh[256][8];
-  const int t = threadIdx.x;
+// One 256-thread block reduces nparts per-tile partials (fixed order) into o
+// and, when record != 0, advances the windowed flow-rate test.
+__device__ __forceinline__ void obs_reduce_block(const double *partials, int nparts, ObsDev *o,
+                                                 double inv_nx, int W, int m, double eps,
+                                                 int record, double (*sh)[8]) {
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int p = t; p < nparts; p += 256)
     for (int k = 0; k < 8; ++k) acc[k] = (k == 7) ? fmax(acc[k], partials[(size_t)p * 8 + k])
                                                   : acc[k] + partials[(size_t)p * 8 + k];
+  __syncthreads();
   for (int k = 0; k < 8; ++k) sh[t][k] = acc[k];
   __syncthreads();
   for (int s = 128; s >= 1; s >>= 1) {
@@ -642,10 +701,17 @@ __global__ __launch_bounds__(256) void k_obs_reduce(const double *partials, int 
   }
 }
 
+static __global__ __launch_bounds__(256) void k_obs_reduce(const double *partials, int nparts,
+                                                    ObsDev *o, double inv_nx, int W, int m,
+                                                    double eps, int record) {
+  __shared__ double sh[256][8];
+  obs_reduce_block(partials, nparts, o, inv_nx, W, m, eps, record, sh);
+}
+
 // Streaming copy used as the achievable-bandwidth reference: one 16-byte
 // vector per thread, non-temporal loads and stores (the fastest plain copy
 // pattern measured on MI355X); init != 0 fills the source instead.
-__global__ __launch_bounds__(256) void k_copy_probe(float4 *src, float4 *dst, int64_t n4, int init) {
+static __global__ __launch_bounds__(256) void k_copy_probe(float4 *src, float4 *dst, int64_t n4, int init) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n4) return;
   if (init) {
@@ -661,6 +727,179 @@ __global__ __launch_bounds__(256) void k_copy_probe(float4 *src, float4 *dst, in
   __builtin_nontemporal_store(v.y, &dst[k].y);
   __builtin_nontemporal_store(v.z, &dst[k].z);
   __builtin_nontemporal_store(v.w, &dst[k].w);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched stepping of many independent lattices ("channels") of uneven size.
+// Each channel keeps its own Args (two per channel: one per ping-pong parity);
+// channels never synchronise with each other.
+
+// Per-channel bookkeeping shared by the batched kernels.
+struct ChanCtl {
+  ObsDev *obs;          // the channel's observables record
+  double *partials;     // the channel's per-tile partials
+  int32_t n_main;       // main tiles (= partial slots)
+  int32_t n_phase;      // phase tiles
+  int32_t active;       // 0 once retired (converged)
+  int32_t retire;       // retire when the convergence flag rises
+  int64_t t;            // steps completed
+  double inv_nx;
+  int32_t W, m;
+  double eps;
+  int32_t obs_every;
+  int32_t parity;       // state copy holding the current state
+};
+
+// Tile of a batched launch: channel and tile index within it.
+struct TileRef {
+  int32_t chan, tile;
+};
+
+template <int D, typename S, typename R, int TZP>
+__global__ __launch_bounds__(256) void k_phase_batch(const Args<S, R> *__restrict__ args,
+                                                     ChanCtl *ctl, const TileRef *__restrict__ tiles) {
+  constexpr int TS = PhaseTile<D, TZP>::TS;
+  __shared__ R ta[TS];
+  __shared__ float tB[D * TS];
+  const TileRef tr = tiles[blockIdx.x];
+  const ChanCtl &c = ctl[tr.chan];
+  if (!c.active) return;  // uniform per block
+  const Args<S, R> &A = args[2 * tr.chan + c.parity];
+  int bx, by, bz;
+  phase_decode<D, TZP>(A.nx, A.ny, tr.tile, bx, by, bz);
+  phase_tile<D, S, R, PULL, TZP>(A, bx, by, bz, ta, tB);
+}
+
+template <int D, typename S, typename R, int BY, int TZ, int H>
+__global__ __launch_bounds__(64 * BY) void k_main_batch(const Args<S, R> *__restrict__ args,
+                                                        ChanCtl *ctl, const TileRef *__restrict__ tiles) {
+  __shared__ R tile[MainTile<D, BY, TZ, H>::TS];
+  __shared__ double red[BY][8];
+  const TileRef tr = tiles[blockIdx.x];
+  const ChanCtl &c = ctl[tr.chan];
+  if (!c.active) return;  // uniform per block
+  const Args<S, R> &A = args[2 * tr.chan + c.parity];
+  int bx, by, bz;
+  main_decode<D, BY>(A.nx, A.ny, tr.tile, bx, by, bz);
+  const bool rec = c.obs_every > 0 && (c.t % c.obs_every) == 0;
+  if (rec) main_tile<D, S, R, PULL, STEP_OBS, BY, TZ, H>(A, bx, by, bz, tr.tile, tile, red);
+  else main_tile<D, S, R, PULL, STEP, BY, TZ, H>(A, bx, by, bz, tr.tile, tile, red);
+}
+
+// End of a batched step, one block per channel: observables when recorded,
+// retirement, step count and parity flip.
+static __global__ __launch_bounds__(256) void k_batch_end(ChanCtl *ctl) {
+  __shared__ double sh[256][8];
+  ChanCtl &c = ctl[blockIdx.x];
+  if (!c.active) return;
+  const bool rec = c.obs_every > 0 && (c.t % c.obs_every) == 0;
+  if (rec) obs_reduce_block(c.partials, c.n_main, c.obs, c.inv_nx, c.W, c.m, c.eps, 1, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c.t += 1;
+    c.parity ^= 1;
+    if (c.retire && c.obs->converged) c.active = 0;
+  }
+}
+
+// Per-channel barrier of a persistent launch: every wave publishes its writes
+// at agent scope, one lane counts the block in and waits (bounded) until all
+// `target` arrivals of the channel's group are in, then acquires.  Returns
+// false if the wait exceeded the spin limit or another block failed; the
+// caller then leaves its loop, so every wave exits.
+__device__ __forceinline__ bool group_barrier(uint32_t *cnt, uint32_t target, int32_t *err,
+                                              int *flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    uint32_t spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(4);
+      if (++spins > (1u << 22) ||
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    *flag = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *flag != 0;
+}
+
+// Persistent batched stepping: block b works for channel chan_of[b] as rank
+// rank_of[b] of a group of group[c] blocks (groups sized by channel work).
+// Per step: phase tiles, channel barrier, retirement check, main tiles,
+// channel barrier; then the group's rank 0 reduces the observables of a
+// recorded step and advances the channel record (step count, parity, active),
+// which the other blocks read only after the next phase barrier.  Parity is
+// tracked locally from the value read before the first barrier.  Must be
+// launched cooperatively (all blocks resident).
+template <int D, typename S, typename R, int TZP, int BY, int TZ, int H>
+__global__ __launch_bounds__(256) void k_persistent(const Args<S, R> *__restrict__ args,
+                                                    ChanCtl *ctl, const int32_t *__restrict__ chan_of,
+                                                    const int32_t *__restrict__ rank_of,
+                                                    const int32_t *__restrict__ group,
+                                                    uint32_t *bar, int32_t *err, int nsteps) {
+  static_assert(BY == 4, "persistent blocks are 64 x 4 threads");
+  constexpr int PTS = PhaseTile<D, TZP>::TS, MTS = MainTile<D, BY, TZ, H>::TS;
+  constexpr int PB = PTS * (int)sizeof(R) + D * PTS * 4, MB = MTS * (int)sizeof(R);
+  constexpr int RB = 256 * 8 * 8;
+  constexpr int LDS = PB > MB ? (PB > RB ? PB : RB) : (MB > RB ? MB : RB);
+  __shared__ double lds[(LDS + 7) / 8];
+  __shared__ double red[BY][8];
+  __shared__ int flag;
+  R *ta = reinterpret_cast<R *>(lds);
+  float *tB = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + PTS * sizeof(R));
+  R *tile = reinterpret_cast<R *>(lds);
+  double(*sh)[8] = reinterpret_cast<double(*)[8]>(lds);
+  const int ch = chan_of[blockIdx.x], rank = rank_of[blockIdx.x], g = group[ch];
+  ChanCtl &c = ctl[ch];
+  uint32_t *cnt = bar + ch;
+  uint32_t arrivals = 0;
+  const int par0 = c.parity;
+  if (!c.active) return;  // retired before this launch: the same in every block
+  for (int st = 0; st < nsteps; ++st) {
+    const int par = par0 ^ (st & 1);
+    const Args<S, R> &A = args[2 * ch + par];
+    for (int k = rank; k < c.n_phase; k += g) {
+      int bx, by, bz;
+      phase_decode<D, TZP>(A.nx, A.ny, k, bx, by, bz);
+      phase_tile<D, S, R, PULL, TZP>(A, bx, by, bz, ta, tB);
+    }
+    arrivals += g;
+    if (!group_barrier(cnt, arrivals, err, &flag)) break;
+    if (!c.active) break;  // retired at the end of the previous step
+    const bool rec = c.obs_every > 0 && (c.t % c.obs_every) == 0;
+    for (int k = rank; k < c.n_main; k += g) {
+      int bx, by, bz;
+      main_decode<D, BY>(A.nx, A.ny, k, bx, by, bz);
+      if (rec) main_tile<D, S, R, PULL, STEP_OBS, BY, TZ, H>(A, bx, by, bz, k, tile, red);
+      else main_tile<D, S, R, PULL, STEP, BY, TZ, H>(A, bx, by, bz, k, tile, red);
+    }
+    arrivals += g;
+    if (!group_barrier(cnt, arrivals, err, &flag)) break;
+    if (rank == 0) {
+      if (rec) obs_reduce_block(c.partials, c.n_main, c.obs, c.inv_nx, c.W, c.m, c.eps, 1, sh);
+      if (threadIdx.x == 0 && threadIdx.y == 0) {
+        c.t += 1;
+        c.parity = par ^ 1;
+        if (c.retire && c.obs->converged) c.active = 0;
+      }
+    }
+  }
+}
+
+// Fills n 32-bit words with v (used instead of a memset so the reset can sit
+// inside a captured graph).
+static __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 }  // namespace lbk

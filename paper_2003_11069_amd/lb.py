@@ -75,6 +75,14 @@ def load_library(path: str = LIB_PATH):
         "lb_profile": ([vp, C.c_int], C.c_int),
         "lb_kernel_times": ([vp, dp, dp, P(C.c_int64)], C.c_int),
         "lb_copy_probe": ([C.c_int64, C.c_int, vp, dp, dp], C.c_int),
+        "lb_batch_create": ([P(lb_params), C.c_int32, vp, P(vp)], C.c_int),
+        "lb_batch_init_fields": ([vp, C.c_int32, dp, dp, dp], C.c_int),
+        "lb_batch_step": ([vp, C.c_int64, C.c_int32], C.c_int),
+        "lb_batch_observables": ([vp, C.c_int32, P(lb_obs)], C.c_int),
+        "lb_batch_get_fields": ([vp, C.c_int32, dp, dp, dp], C.c_int),
+        "lb_batch_info": ([vp, C.c_int32, P(C.c_int64), P(C.c_int32), P(C.c_int32)], C.c_int),
+        "lb_batch_graphs": ([vp], C.c_int),
+        "lb_batch_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -260,3 +268,71 @@ class Lattice:
         psi = np.zeros(self.N); fr = np.zeros(self.p.dim * self.N); hit = np.zeros(self.N, np.int32)
         _check(self.lib.lb_get_nci(self.h, _dp(psi), _dp(fr), _ip(hit)))
         return psi, fr.reshape(self.p.dim, self.N), hit
+
+
+LB_BATCH_LAUNCH, LB_BATCH_PERSISTENT = 0, 1
+
+
+def _obs_dict(o: lb_obs, rc: int) -> dict:
+    return {"step": o.step, "mass": np.array(o.mass[:]), "mom": np.array(o.mom[:]), "Q": o.Q,
+            "Q_d": o.Q_d, "umax": o.umax, "Q_window": o.Q_window,
+            "converged": bool(o.converged), "flags": o.flags, "rc": rc}
+
+
+class Batch:
+    """Many independent lattices stepped together (lb_batch_* ABI)."""
+
+    def __init__(self, params: list, stream: int | None = None):
+        self.lib = load_library()
+        self.params = list(params)
+        arr = (lb_params * len(self.params))(*[p.to_c() for p in self.params])
+        self._arr = arr
+        h = C.c_void_p()
+        st = current_stream_handle() if stream is None else stream
+        _check(self.lib.lb_batch_create(arr, len(self.params), C.c_void_p(st), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __len__(self):
+        return len(self.params)
+
+    def init_fields(self, c: int, rho1, rho2, u=None):
+        p = self.params[c]
+        r1 = np.ascontiguousarray(rho1, np.float64).ravel()
+        r2 = np.ascontiguousarray(rho2, np.float64).ravel()
+        if r1.size != p.N or r2.size != p.N:
+            raise ValueError("density arrays must hold N values")
+        uu = None if u is None else np.ascontiguousarray(u, np.float64).ravel()
+        _check(self.lib.lb_batch_init_fields(self.h, int(c), _dp(r1), _dp(r2), _dp(uu)))
+
+    def step(self, n: int, mode: int = LB_BATCH_PERSISTENT):
+        _check(self.lib.lb_batch_step(self.h, int(n), int(mode)))
+
+    def observables(self, c: int) -> dict:
+        o = lb_obs()
+        rc = self.lib.lb_batch_observables(self.h, int(c), C.byref(o))
+        if rc < 0 and rc != -4:
+            _check(rc)
+        return _obs_dict(o, rc)
+
+    def fields(self, c: int):
+        p = self.params[c]
+        r1 = np.zeros(p.N); r2 = np.zeros(p.N); u = np.zeros(p.dim * p.N)
+        _check(self.lib.lb_batch_get_fields(self.h, int(c), _dp(r1), _dp(r2), _dp(u)))
+        return r1, r2, u.reshape(p.dim, p.N)
+
+    def info(self, c: int) -> dict:
+        st = C.c_int64(); act = C.c_int32(); blk = C.c_int32()
+        _check(self.lib.lb_batch_info(self.h, int(c), C.byref(st), C.byref(act), C.byref(blk)))
+        return {"steps": st.value, "active": bool(act.value), "blocks": blk.value}
+
+    @property
+    def graphs(self) -> bool:
+        return self.lib.lb_batch_graphs(self.h) == 1
