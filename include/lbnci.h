@@ -177,6 +177,7 @@ typedef struct lb_batch lb_batch;
                                  tile table of all channels, replayed from a hipGraph */
 #define LB_BATCH_PERSISTENT 1 /* one cooperative persistent launch for all steps; each
                                  channel synchronises only its own group of blocks */
+#define LB_BATCH_AUTO 2       /* the configuration chosen by lb_batch_tune / set_config */
 
 /* p: n parameter sets.  Creates n handles on the stream plus the tile tables
  * and persistent-launch groups.  Errors as lb_create, and LB_EINVAL when the
@@ -199,6 +200,15 @@ int lb_batch_info(lb_batch *b, int32_t c, int64_t *steps, int32_t *active, int32
 /* 1 while both modes run from hipGraphs, 0 after a graph path failed and
  * direct launches are used. */
 int lb_batch_graphs(lb_batch *b);
+/* Autotuner: times each candidate configuration (execution mode; tile order:
+ * 0 = each XCD receives a contiguous range of tiles, 1 = channel order; main
+ * tile height 4/8/16 rows for D2Q9) over trial_steps real steps (they advance
+ * the channels, plus 2 warm-up steps per candidate) and keeps the fastest as
+ * the batch's configuration (used by mode LB_BATCH_AUTO).  best_ms_per_step
+ * may be NULL. */
+int lb_batch_tune(lb_batch *b, int32_t trial_steps, double *best_ms_per_step);
+int lb_batch_set_config(lb_batch *b, int32_t mode, int32_t tile_order, int32_t main_by);
+int lb_batch_get_config(lb_batch *b, int32_t *mode, int32_t *tile_order, int32_t *main_by);
 void lb_batch_destroy(lb_batch *b);
 
 /* Thread-local message of the last failure ("" if none). */

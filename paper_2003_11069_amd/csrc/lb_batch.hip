@@ -51,6 +51,10 @@ struct lb_batch {
   int graph_ok = 1;              // 0 once a graph path failed (direct launches used)
   int64_t bytes = 0;
   int own_stream = 0;            // stream created by the batch (caller passed NULL)
+  // execution configuration (chosen by lb_batch_tune or lb_batch_set_config)
+  int cfg_mode = LB_BATCH_LAUNCH;
+  int cfg_order = 0;             // 0: tiles dealt so each XCD gets a contiguous range; 1: channel order
+  int cfg_by = 0;                // main-tile height of the launch mode (0 = library default)
 };
 
 namespace {
@@ -72,15 +76,21 @@ int phase_count(const lb_batch *b, const lb_params &p) {
 int main_count(const lb_batch *b, const lb_params &p) {
   return b->D == 2 ? main_tiles<2, BY2, TZ2>(p.nx, p.ny, p.nz) : main_tiles<3, BY3, TZ3>(p.nx, p.ny, p.nz);
 }
+// main tiles of the launch mode with tile height `by` (2-D: 4, 8 or 16)
+int main_count_by(const lb_batch *b, const lb_params &p, int by) {
+  if (b->D == 3 || by == 0 || by == BY2) return main_count(b, p);
+  return by == 8 ? main_tiles<2, 8, 1>(p.nx, p.ny, p.nz) : main_tiles<2, 16, 1>(p.nx, p.ny, p.nz);
+}
 
 // Tile table of all channels, ordered so that each XCD (blocks are dealt
 // round-robin over the 8 XCDs) receives a contiguous range of the flat list.
-std::vector<TileRef> tile_table(const lb_batch *b, bool phase) {
+std::vector<TileRef> tile_table(const lb_batch *b, bool phase, int order, int by) {
   std::vector<TileRef> flat;
   for (int c = 0; c < b->n; ++c) {
-    const int nt = phase ? phase_count(b, b->h[c]->p) : main_count(b, b->h[c]->p);
+    const int nt = phase ? phase_count(b, b->h[c]->p) : main_count_by(b, b->h[c]->p, by);
     for (int k = 0; k < nt; ++k) flat.push_back(TileRef{c, k});
   }
+  if (order == 1) return flat;
   const int nb = (int)flat.size();
   std::vector<TileRef> t(nb);
   const int q = nb >> 3, r = nb & 7;
@@ -218,8 +228,15 @@ void launch_step(lb_batch *b) {
   if constexpr (D == 2) {
     hipLaunchKernelGGL((k_phase_batch<2, S, R, 1>), dim3(b->n_phase), dim3(64, 4), 0, b->stream, args,
                        b->d_ctl, b->d_phase);
-    hipLaunchKernelGGL((k_main_batch<2, S, R, BY2, TZ2, H2>), dim3(b->n_main), dim3(64, BY2), 0,
-                       b->stream, args, b->d_ctl, b->d_main);
+    if (b->cfg_by == 8)
+      hipLaunchKernelGGL((k_main_batch<2, S, R, 8, 1, H2>), dim3(b->n_main), dim3(64, 8), 0, b->stream,
+                         args, b->d_ctl, b->d_main);
+    else if (b->cfg_by == 16)
+      hipLaunchKernelGGL((k_main_batch<2, S, R, 16, 1, H2>), dim3(b->n_main), dim3(64, 16), 0, b->stream,
+                         args, b->d_ctl, b->d_main);
+    else
+      hipLaunchKernelGGL((k_main_batch<2, S, R, BY2, TZ2, H2>), dim3(b->n_main), dim3(64, BY2), 0,
+                         b->stream, args, b->d_ctl, b->d_main);
   } else {
     hipLaunchKernelGGL((k_phase_batch<3, S, R, TZP3>), dim3(b->n_phase), dim3(64, 4), 0, b->stream,
                        args, b->d_ctl, b->d_phase);
@@ -325,12 +342,13 @@ int ensure_pers_graph(lb_batch *b, int64_t nsteps) {
   return LB_OK;
 }
 
-int upload_ctl(lb_batch *b) {
+int upload_ctl(lb_batch *b, int mode) {
   for (int c = 0; c < b->n; ++c) {
     lb_handle *h = b->h[c];
     ChanCtl &k = b->ctl[c];
     k.t = h->t;
     k.parity = h->cur;
+    k.n_main = mode == LB_BATCH_LAUNCH ? main_count_by(b, h->p, b->cfg_by) : main_count(b, h->p);
   }
   HIP_TRY(hipMemcpyAsync(b->d_ctl, b->ctl.data(), sizeof(ChanCtl) * b->n, hipMemcpyHostToDevice, b->stream));
   return LB_OK;
@@ -342,6 +360,36 @@ int download_ctl(lb_batch *b) {
   for (int c = 0; c < b->n; ++c) {
     b->h[c]->t = b->ctl[c].t;
     b->h[c]->cur = b->ctl[c].parity;
+  }
+  return LB_OK;
+}
+
+int apply_config(lb_batch *b, int mode, int order, int by) {
+  if (b->D == 3) by = 0;
+  if (by != 0 && by != 4 && by != 8 && by != 16) return fail(LB_EINVAL, "main-tile height must be 4, 8 or 16");
+  if (mode != LB_BATCH_LAUNCH && mode != LB_BATCH_PERSISTENT) return fail(LB_EINVAL, "unknown mode");
+  if (order != 0 && order != 1) return fail(LB_EINVAL, "unknown tile order");
+  if (by == 4) by = 0;
+  if (b->d_main && order == b->cfg_order && by == b->cfg_by) {
+    b->cfg_mode = mode;
+    return LB_OK;
+  }
+  auto tp = tile_table(b, true, order, 0), tm = tile_table(b, false, order, by);
+  if (b->d_phase) (void)hipFree(b->d_phase);
+  if (b->d_main) (void)hipFree(b->d_main);
+  b->d_phase = b->d_main = nullptr;
+  HIP_TRY(hipMalloc(&b->d_phase, sizeof(TileRef) * tp.size()));
+  HIP_TRY(hipMalloc(&b->d_main, sizeof(TileRef) * tm.size()));
+  HIP_TRY(hipMemcpy(b->d_phase, tp.data(), sizeof(TileRef) * tp.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_main, tm.data(), sizeof(TileRef) * tm.size(), hipMemcpyHostToDevice));
+  b->n_phase = (int)tp.size();
+  b->n_main = (int)tm.size();
+  b->cfg_mode = mode;
+  b->cfg_order = order;
+  b->cfg_by = by;
+  if (b->launch_graph) {  // recorded with the previous tables
+    (void)hipGraphExecDestroy(b->launch_graph);
+    b->launch_graph = nullptr;
   }
   return LB_OK;
 }
@@ -405,15 +453,9 @@ int lb_batch_create(const lb_params *p, int32_t n, void *hip_stream, lb_batch **
     hipError_t e = hipMalloc(&b->d_ctl, sizeof(ChanCtl) * n);
     if (e != hipSuccess) rc = fail(LB_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
   }
+  if (!rc) rc = apply_config(b, LB_BATCH_LAUNCH, 0, 0);
   if (!rc) {
-    auto tp = tile_table(b, true), tm = tile_table(b, false);
-    b->n_phase = (int)tp.size();
-    b->n_main = (int)tm.size();
-    hipError_t e = hipMalloc(&b->d_phase, sizeof(TileRef) * tp.size());
-    if (e == hipSuccess) e = hipMalloc(&b->d_main, sizeof(TileRef) * tm.size());
-    if (e == hipSuccess) e = hipMemcpy(b->d_phase, tp.data(), sizeof(TileRef) * tp.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_main, tm.data(), sizeof(TileRef) * tm.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&b->d_bar, sizeof(uint32_t) * n);
+    hipError_t e = hipMalloc(&b->d_bar, sizeof(uint32_t) * n);
     if (e == hipSuccess) e = hipMalloc(&b->d_err, sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(int32_t));
     if (e != hipSuccess) rc = fail(LB_EDEVICE, "batch tables: %s", hipGetErrorString(e));
@@ -458,6 +500,7 @@ int lb_batch_init_fields(lb_batch *b, int32_t c, const double *rho1, const doubl
 
 int lb_batch_step(lb_batch *b, int64_t n, int32_t mode) {
   if (!b || n < 0) return fail(LB_EINVAL, "bad arguments");
+  if (mode == LB_BATCH_AUTO) mode = b->cfg_mode;
   if (mode != LB_BATCH_LAUNCH && mode != LB_BATCH_PERSISTENT) return fail(LB_EINVAL, "unknown mode");
   for (lb_handle *h : b->h)
     if (!h->initialised) return fail(LB_ESTATE, "every channel must be initialised");
@@ -476,7 +519,7 @@ int lb_batch_step(lb_batch *b, int64_t n, int32_t mode) {
     }
     steps -= 1;
   }
-  int rc = upload_ctl(b);
+  int rc = upload_ctl(b, mode);
   if (rc) return rc;
   if (steps == 0) {
   } else if (mode == LB_BATCH_LAUNCH) {
@@ -533,5 +576,56 @@ int lb_batch_info(lb_batch *b, int32_t c, int64_t *steps, int32_t *active, int32
 }
 
 int lb_batch_graphs(lb_batch *b) { return b ? b->graph_ok : -1; }
+
+int lb_batch_set_config(lb_batch *b, int32_t mode, int32_t tile_order, int32_t main_by) {
+  if (!b) return fail(LB_EINVAL, "NULL batch");
+  return apply_config(b, mode, tile_order, main_by);
+}
+
+int lb_batch_get_config(lb_batch *b, int32_t *mode, int32_t *tile_order, int32_t *main_by) {
+  if (!b) return fail(LB_EINVAL, "NULL batch");
+  if (mode) *mode = b->cfg_mode;
+  if (tile_order) *tile_order = b->cfg_order;
+  if (main_by) *main_by = b->cfg_by == 0 ? (b->D == 2 ? BY2 : BY3) : b->cfg_by;
+  return LB_OK;
+}
+
+int lb_batch_tune(lb_batch *b, int32_t trial_steps, double *best_ms_per_step) {
+  if (!b || trial_steps < 1) return fail(LB_EINVAL, "bad arguments");
+  struct Cand { int mode, order, by; };
+  std::vector<Cand> cands;
+  const std::vector<int> bys = b->D == 2 ? std::vector<int>{4, 8, 16} : std::vector<int>{4};
+  for (int order = 0; order < 2; ++order)
+    for (int by : bys) cands.push_back({LB_BATCH_LAUNCH, order, by});
+  cands.push_back({LB_BATCH_PERSISTENT, 0, 4});
+  double best = 1e300;
+  Cand win = cands[0];
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = LB_OK;
+  for (const Cand &c : cands) {
+    rc = apply_config(b, c.mode, c.order, c.by);
+    if (!rc) rc = lb_batch_step(b, 2, c.mode);  // warm-up (also records the graph)
+    if (rc) break;
+    HIP_TRY(hipEventRecord(e0, b->stream));
+    rc = lb_batch_step(b, trial_steps, c.mode);
+    if (rc) break;
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    const double per = ms / trial_steps;
+    if (per < best) {
+      best = per;
+      win = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (best_ms_per_step) *best_ms_per_step = best;
+  return apply_config(b, win.mode, win.order, win.by);
+}
 
 }  // extern "C"

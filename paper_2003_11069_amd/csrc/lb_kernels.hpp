@@ -803,32 +803,35 @@ static __global__ __launch_bounds__(256) void k_batch_end(ChanCtl *ctl) {
   }
 }
 
-// Per-channel barrier of a persistent launch: every wave publishes its writes
-// at agent scope, one lane counts the block in and waits (bounded) until all
-// `target` arrivals of the channel's group are in, then acquires.  Returns
-// false if the wait exceeded the spin limit or another block failed; the
-// caller then leaves its loop, so every wave exits.
+// Per-channel barrier of a persistent launch.  Every wave waits until its own
+// stores are complete in L2, then one lane per block publishes the block's
+// writes at agent scope (one L2 write-back), counts the block in and waits
+// (bounded) until all `target` arrivals of the channel's group are in, then
+// acquires at agent scope (one L1/L2 invalidation) before the block goes on.
+// Returns false if the wait exceeded 2 s or another block failed;
+// the caller then leaves its loop, so every wave exits.
 __device__ __forceinline__ bool group_barrier(uint32_t *cnt, uint32_t target, int32_t *err,
                                               int *flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     uint32_t spins = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(4);
-      if (++spins > (1u << 22) ||
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz constant clock
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 26) || __builtin_amdgcn_s_memrealtime() - t0 > 200000000ull ||
           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *flag = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *flag != 0;
 }
 

@@ -83,6 +83,9 @@ def load_library(path: str = LIB_PATH):
         "lb_batch_info": ([vp, C.c_int32, P(C.c_int64), P(C.c_int32), P(C.c_int32)], C.c_int),
         "lb_batch_graphs": ([vp], C.c_int),
         "lb_batch_destroy": ([vp], None),
+        "lb_batch_tune": ([vp, C.c_int32, dp], C.c_int),
+        "lb_batch_set_config": ([vp, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+        "lb_batch_get_config": ([vp, P(C.c_int32), P(C.c_int32), P(C.c_int32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -270,7 +273,7 @@ class Lattice:
         return psi, fr.reshape(self.p.dim, self.N), hit
 
 
-LB_BATCH_LAUNCH, LB_BATCH_PERSISTENT = 0, 1
+LB_BATCH_LAUNCH, LB_BATCH_PERSISTENT, LB_BATCH_AUTO = 0, 1, 2
 
 
 def _obs_dict(o: lb_obs, rc: int) -> dict:
@@ -312,7 +315,7 @@ class Batch:
         uu = None if u is None else np.ascontiguousarray(u, np.float64).ravel()
         _check(self.lib.lb_batch_init_fields(self.h, int(c), _dp(r1), _dp(r2), _dp(uu)))
 
-    def step(self, n: int, mode: int = LB_BATCH_PERSISTENT):
+    def step(self, n: int, mode: int = 2):
         _check(self.lib.lb_batch_step(self.h, int(n), int(mode)))
 
     def observables(self, c: int) -> dict:
@@ -336,3 +339,42 @@ class Batch:
     @property
     def graphs(self) -> bool:
         return self.lib.lb_batch_graphs(self.h) == 1
+
+    def signature(self) -> str:
+        """Shape class of the batch for the tuning cache: lattice, storage and
+        the sorted channel sizes rounded to tiles."""
+        p0 = self.params[0]
+        sizes = sorted(((p.nx + 63) // 64, (p.ny + 3) // 4, p.nz) for p in self.params)
+        return f"L{p0.lattice}-S{p0.storage}-" + "_".join(f"{a}x{b}x{c}" for a, b, c in sizes)
+
+    def config(self) -> dict:
+        m = C.c_int32(); o = C.c_int32(); b = C.c_int32()
+        _check(self.lib.lb_batch_get_config(self.h, C.byref(m), C.byref(o), C.byref(b)))
+        return {"mode": m.value, "tile_order": o.value, "main_by": b.value}
+
+    def set_config(self, mode: int, tile_order: int, main_by: int):
+        _check(self.lib.lb_batch_set_config(self.h, int(mode), int(tile_order), int(main_by)))
+
+    def tune(self, trial_steps: int = 20, cache: str | None = None) -> dict:
+        """Picks the fastest configuration (lb_batch_tune), or reuses the one
+        cached for this batch's signature in the JSON file `cache`.  Trial steps
+        are real steps of the channels."""
+        import json
+        key = self.signature()
+        db = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                db = json.load(f)
+        if key in db:
+            cfg = db[key]
+            self.set_config(cfg["mode"], cfg["tile_order"], cfg["main_by"])
+            return dict(cfg, cached=True)
+        ms = C.c_double()
+        _check(self.lib.lb_batch_tune(self.h, int(trial_steps), C.byref(ms)))
+        cfg = dict(self.config(), ms_per_step=ms.value)
+        if cache:
+            db[key] = cfg
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(db, f, indent=1)
+        return dict(cfg, cached=False)

@@ -106,3 +106,25 @@ def test_batch_retirement(mode):
         # flux of the discrete parabola over the H fluid rows (midpoint sum)
         q = 1e-6 * H ** 3 / (12 * nu) * (1 + 1 / (2 * H * H))
         assert ob["Q_window"] == pytest.approx(q, rel=1e-2)
+
+
+def test_batch_tuner(tmp_path):
+    """The autotuner's trial steps are real steps: after tuning, every channel
+    equals a single lattice advanced by the same number of steps; the choice
+    is cached per shape signature and reused."""
+    say("[gpu] batch tuner")
+    b, ps = _batch(CASES)
+    cache = str(tmp_path / "tune.json")
+    cfg = b.tune(trial_steps=4, cache=cache)
+    say(f"  chosen {cfg}")
+    b.step(10, P.LB_BATCH_AUTO)
+    for k, c in enumerate(CASES):
+        n = b.info(k)["steps"]
+        g = P.Lattice(ps[k])
+        g.init_fields(c.rho1, c.rho2)
+        g.step(n)
+        for x, y in zip(b.fields(k), g.fields()):
+            assert np.array_equal(x, y), f"channel {k}"
+    b2, _ = _batch(CASES)
+    cfg2 = b2.tune(trial_steps=4, cache=cache)
+    assert cfg2["cached"] and cfg2["mode"] == cfg["mode"] and cfg2["main_by"] == cfg["main_by"]
