@@ -221,3 +221,96 @@ def random_fields(p: dict, seed=0, amp=0.05, umax=0.02) -> Case:
     r2 = (rho * 0.5 * (1 - psi)).ravel()
     u = umax * rng.uniform(-1, 1, (dim, nx * ny * nz))
     return Case(dict(p), r1, r2, u)
+
+
+# --- warm-start network inputs -----------------------------------------------
+
+def unet_segments(levels: int, base: int):
+    """(weight count, fan-in, bias count) of each layer of the warm-start U-Net
+    in its flat parameter order: encoder levels 0..L-1 (two 3x3 convs each,
+    input padded to 8 channels), decoder levels L-2..0 (2x2 up-sampling, two
+    3x3 convs over [up | skip]), 1x1 head with 8 outputs."""
+    C = [base << l for l in range(levels)]
+    seg = []
+    for l in range(levels):
+        cin = 8 if l == 0 else C[l - 1]
+        seg.append((C[l] * 9 * cin, 9 * cin, C[l]))
+        seg.append((C[l] * 9 * C[l], 9 * C[l], C[l]))
+    for l in range(levels - 2, -1, -1):
+        seg.append((4 * C[l] * C[l + 1], C[l + 1], C[l]))
+        seg.append((C[l] * 9 * 2 * C[l], 9 * 2 * C[l], C[l]))
+        seg.append((C[l] * 9 * C[l], 9 * C[l], C[l]))
+    seg.append((8 * base, base, 8))
+    return seg
+
+
+def unet_params(levels: int, base: int, seed: int = 0, bias: float = 0.05) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / fan-in); the head sqrt(1 / fan-in)) and
+    small uniform biases, float32, flat parameter order of ``unet_segments``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    segs = unet_segments(levels, base)
+    parts = []
+    for k, (nw, fan, nb) in enumerate(segs):
+        gain = 1.0 if k == len(segs) - 1 else 2.0
+        parts.append(rng.normal(0.0, math.sqrt(gain / fan), nw))
+        parts.append(rng.uniform(-bias, bias, nb))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unet_batch(B: int, H: int, W: int, cin: int, cout: int, seed: int = 0):
+    """Smooth random inputs [B,H,W,cin] and targets [B,H,W,cout] (float32):
+    sums of a few random Fourier modes plus white noise."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+
+    def field(n, c):
+        out = np.zeros((n, H, W, c))
+        for b in range(n):
+            for ch in range(c):
+                for _ in range(4):
+                    ky, kx = rng.integers(0, 4, 2)
+                    ph = rng.uniform(0, 2 * np.pi)
+                    out[b, :, :, ch] += rng.normal() * np.cos(2 * np.pi * (ky * yy / H + kx * xx / W) + ph)
+        return out + 0.1 * rng.normal(size=out.shape)
+
+    return field(B, cin).astype(np.float32), field(B, cout).astype(np.float32)
+
+
+def unet_params_exact(levels: int, base: int, seed: int = 0) -> np.ndarray:
+    """Parameters for which every network sum is exact in FP32: each output
+    channel of each layer has one non-zero weight (+1 with probability 3/4,
+    else -1) and a bias in {0, 1, 2, 3} / 16, so activations stay multiples of
+    1/16 below 16 in magnitude (exact in bfloat16)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    C = [base << l for l in range(levels)]
+    parts = []
+
+    def layer(cout, taps, cin):
+        w = np.zeros((cout, taps * cin))
+        k = rng.integers(0, taps * cin, cout)
+        w[np.arange(cout), k] = np.where(rng.uniform(size=cout) < 0.75, 1.0, -1.0)
+        parts.append(w.ravel())
+        parts.append(rng.integers(0, 4, cout) / 16.0)
+
+    for l in range(levels):
+        layer(C[l], 9, 8 if l == 0 else C[l - 1])
+        layer(C[l], 9, C[l])
+    for l in range(levels - 2, -1, -1):
+        w = np.zeros((4, C[l], C[l + 1]))
+        k = rng.integers(0, C[l + 1], (4, C[l]))
+        for d in range(4):
+            w[d, np.arange(C[l]), k[d]] = np.where(rng.uniform(size=C[l]) < 0.75, 1.0, -1.0)
+        parts.append(w.ravel())
+        parts.append(rng.integers(0, 4, C[l]) / 16.0)
+        layer(C[l], 9, 2 * C[l])
+        layer(C[l], 9, C[l])
+    layer(8, 1, base)
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unet_batch_exact(B: int, H: int, W: int, cin: int, cout: int, seed: int = 0):
+    """Inputs and targets that are multiples of 1/16 in [-4, 4) (float32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.integers(-64, 64, (B, H, W, cin)) / 16.0
+    t = rng.integers(-64, 64, (B, H, W, cout)) / 16.0
+    return x.astype(np.float32), t.astype(np.float32)
