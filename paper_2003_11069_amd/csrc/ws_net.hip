@@ -1,0 +1,625 @@
+// ws_net.hip -- U-Net of the learned warm start (C ABI in include/wsnet.h).
+//
+// Architecture (levels L, base channels C0, C_l = C0 << l, image H x W):
+//   encoder level l: conv3x3+ReLU (in -> C_l), conv3x3+ReLU (C_l -> C_l),
+//                    2x2 max pool to level l+1 (l < L-1)
+//   decoder level l (l = L-2 .. 0): 2x2 stride-2 transposed conv (C_{l+1} -> C_l),
+//                    concat [up | encoder output of level l], conv3x3+ReLU
+//                    (2 C_l -> C_l), conv3x3+ReLU (C_l -> C_l)
+//   head: 1x1 conv (C0 -> cout), no activation; loss: mean squared error.
+// Input channels are padded to 8 and head outputs to 8 (padding weights zero).
+//
+// Flat FP32 parameter order (weights then bias of each layer):
+//   for l = 0..L-1:  e1[l].W [C_l][3][3][cin_l], e1[l].b [C_l],
+//                    e2[l].W [C_l][3][3][C_l],   e2[l].b [C_l]      (cin_0 = 8, cin_l = C_{l-1})
+//   for l = L-2..0:  up[l].W [4][C_l][C_{l+1}] (4 = 2 dy + dx), up[l].b [C_l],
+//                    d1[l].W [C_l][3][3][2 C_l], d1[l].b [C_l],
+//                    d2[l].W [C_l][3][3][C_l],   d2[l].b [C_l]
+//   head.W [8][C0], head.b [8]
+#include "wsnet.h"
+#include "ws_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace wsk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HTRY(expr)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(WS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct Conv {
+  int KS, Cin, Cout;
+  bool relu;
+  int64_t w_off, b_off;  // into the flat parameter vector
+  bf16 *Wt = nullptr, *WtT = nullptr;
+  int64_t nw() const { return (int64_t)Cout * KS * KS * Cin; }
+};
+
+struct Up {
+  int Cin, Cout;
+  int64_t w_off, b_off;
+  bf16 *Wt = nullptr, *WtT = nullptr;
+  int64_t nw() const { return 4LL * Cout * Cin; }
+};
+
+template <typename T>
+struct Buf {
+  T *p = nullptr;
+  int cs = 0;  // channel stride
+};
+
+}  // namespace
+
+struct ws_net {
+  ws_config cfg;
+  int L, C0;
+  hipStream_t stream;
+  int64_t np = 0;
+  float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+  int64_t adam_t = 0;
+  std::vector<Conv> e1, e2, d1, d2;
+  std::vector<Up> up;
+  Conv head;
+  // activations (BF16) and gradients (FP32), per level
+  Buf<bf16> xin;                 // packed input, 8 channels
+  std::vector<Buf<bf16>> pool;   // pool output feeding level l (l >= 1)
+  std::vector<Buf<bf16>> mid_e, cat, mid_d, dec;
+  Buf<bf16> bott;                // encoder output of the last level
+  Buf<float> y;                  // head output, 8 channels
+  std::vector<Buf<float>> dpool, dmid_e, dcat, dmid_d, ddec;
+  Buf<float> dbott, dy;
+  float *scratch = nullptr;  // split-K partials
+  size_t scratch_floats = 0;
+  double *loss_part = nullptr, *loss = nullptr;
+  int n_loss_blocks = 0;
+  std::vector<void *> allocs;
+  int64_t bytes = 0;
+};
+
+namespace {
+
+int chans(const ws_net *n, int l) { return n->C0 << l; }
+int imgH(const ws_net *n, int l) { return n->cfg.H >> l; }
+int imgW(const ws_net *n, int l) { return n->cfg.W >> l; }
+
+template <typename T>
+int dalloc(ws_net *n, T **p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) return fail(WS_ENOMEM, "hipMalloc(%zu): %s", count * sizeof(T), hipGetErrorString(e));
+  n->allocs.push_back((void *)*p);
+  n->bytes += (int64_t)(count * sizeof(T));
+  HTRY(hipMemsetAsync(*p, 0, count * sizeof(T), n->stream));
+  return WS_OK;
+}
+
+template <typename T>
+int buf(ws_net *n, Buf<T> &b, int l, int cs) {
+  b.cs = cs;
+  return dalloc(n, &b.p, (size_t)n->cfg.max_batch * imgH(n, l) * imgW(n, l) * cs);
+}
+
+Conv make_conv(int64_t &off, int KS, int Cin, int Cout, bool relu) {
+  Conv c;
+  c.KS = KS;
+  c.Cin = Cin;
+  c.Cout = Cout;
+  c.relu = relu;
+  c.w_off = off;
+  off += c.nw();
+  c.b_off = off;
+  off += Cout;
+  return c;
+}
+
+Up make_up(int64_t &off, int Cin, int Cout) {
+  Up u;
+  u.Cin = Cin;
+  u.Cout = Cout;
+  u.w_off = off;
+  off += u.nw();
+  u.b_off = off;
+  off += Cout;
+  return u;
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+int refresh_weights(ws_net *n) {
+  auto conv = [&](Conv &c) {
+    hipLaunchKernelGGL(k_conv_weights, dim3(blocks(c.nw())), dim3(256), 0, n->stream, n->params + c.w_off, c.Cout,
+                       c.Cin, c.KS, c.Wt, c.WtT);
+  };
+  for (auto &c : n->e1) conv(c);
+  for (auto &c : n->e2) conv(c);
+  for (auto &c : n->d1) conv(c);
+  for (auto &c : n->d2) conv(c);
+  conv(n->head);
+  for (auto &u : n->up)
+    hipLaunchKernelGGL(k_up_weights, dim3(blocks(u.nw())), dim3(256), 0, n->stream, n->params + u.w_off, u.Cout,
+                       u.Cin, u.Wt, u.WtT);
+  HTRY(hipGetLastError());
+  return WS_OK;
+}
+
+template <class Prob>
+void gemm(ws_net *n, const Prob &p, int M, int N, int splits) {
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
+  hipLaunchKernelGGL((k_gemm<Prob>), grid, dim3(256), 0, n->stream, p);
+}
+
+// split count and chunk (pixels per split) for a weight-gradient GEMM
+void split_plan(const ws_net *n, int P, int M, int N, int &splits, int &chunk) {
+  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int s = std::max(1, 1024 / std::max(tiles, 1));
+  s = std::min(s, std::max(1, P / (4 * BK)));
+  chunk = ((P + s - 1) / s + BK - 1) / BK * BK;
+  splits = (P + chunk - 1) / chunk;
+  (void)n;
+}
+
+template <int KS, bool RELU, bool F32>
+int conv_fwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> out, View<float> outf) {
+  ConvFwd<KS, RELU, F32> p;
+  p.g = g;
+  p.in = in;
+  p.Cin = c.Cin;
+  p.Cout = c.Cout;
+  p.Wt = c.Wt;
+  p.bias = n->params + c.b_off;
+  p.out = out;
+  p.outf = outf;
+  gemm(n, p, g.B * g.H * g.W, c.Cout, 1);
+  return WS_OK;
+}
+
+int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> out) {
+  return c.relu ? conv_fwd_t<3, true, false>(n, c, g, in, out, View<float>{nullptr, 0, 0})
+                : conv_fwd_t<3, false, false>(n, c, g, in, out, View<float>{nullptr, 0, 0});
+}
+
+// weight and bias gradients of a conv layer, then (if din.p) its data gradient
+template <int KS, bool RELU>
+int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act, View<const float> dout,
+               View<float> din, int accumulate) {
+  const int P = g.B * g.H * g.W;
+  const int Kw = KS * KS * c.Cin;
+  int splits, chunk;
+  split_plan(n, P, c.Cout, Kw + 1, splits, chunk);
+  if ((size_t)splits * c.Cout * (Kw + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+  ConvBwdWeight<KS, RELU> pw;
+  pw.g = g;
+  pw.dout = dout;
+  pw.act = act;
+  pw.in = in;
+  pw.Cin = c.Cin;
+  pw.Cout = c.Cout;
+  pw.chunk = chunk;
+  pw.partial = n->scratch;
+  gemm(n, pw, c.Cout, Kw + 1, splits);
+  hipLaunchKernelGGL(k_split_reduce, dim3(blocks((int64_t)c.Cout * Kw)), dim3(256), 0, n->stream, n->scratch, splits,
+                     c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
+  if (din.p) {
+    ConvBwdData<KS, RELU> pd;
+    pd.g = g;
+    pd.dout = dout;
+    pd.act = act;
+    pd.Cin = c.Cin;
+    pd.Cout = c.Cout;
+    pd.WtT = c.WtT;
+    pd.din = din;
+    pd.accumulate = accumulate;
+    gemm(n, pd, P, c.Cin, 1);
+  }
+  return WS_OK;
+}
+
+int up_fwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<bf16> out) {
+  UpFwd p;
+  p.g = gin;
+  p.in = in;
+  p.Cin = u.Cin;
+  p.Cout = u.Cout;
+  p.Wt = u.Wt;
+  p.bias = n->params + u.b_off;
+  p.out = out;
+  gemm(n, p, 4 * gin.B * gin.H * gin.W, u.Cout, 1);
+  return WS_OK;
+}
+
+int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const float> dout, View<float> din) {
+  const int P = gin.B * gin.H * gin.W;
+  int splits, chunk;
+  split_plan(n, P, 4 * u.Cout, u.Cin + 1, splits, chunk);
+  if ((size_t)splits * 4 * u.Cout * (u.Cin + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+  UpBwdWeight pw;
+  pw.g = gin;
+  pw.dout = dout;
+  pw.in = in;
+  pw.Cin = u.Cin;
+  pw.Cout = u.Cout;
+  pw.chunk = chunk;
+  pw.partial = n->scratch;
+  gemm(n, pw, 4 * u.Cout, u.Cin + 1, splits);
+  hipLaunchKernelGGL(k_split_reduce, dim3(blocks((int64_t)4 * u.Cout * u.Cin)), dim3(256), 0, n->stream, n->scratch,
+                     splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
+  UpBwdData pd;
+  pd.g = gin;
+  pd.dout = dout;
+  pd.Cin = u.Cin;
+  pd.Cout = u.Cout;
+  pd.WtT = u.WtT;
+  pd.din = din;
+  gemm(n, pd, P, u.Cin, 1);
+  return WS_OK;
+}
+
+template <typename T>
+View<const T> cv(const Buf<T> &b, int coff = 0) { return View<const T>{b.p, b.cs, coff}; }
+template <typename T>
+View<T> mv(Buf<T> &b, int coff = 0) { return View<T>{b.p, b.cs, coff}; }
+
+int forward(ws_net *n, const float *x, int B) {
+  const int L = n->L;
+  const int P0 = B * n->cfg.H * n->cfg.W;
+  hipLaunchKernelGGL(k_pack_input, dim3(blocks((int64_t)P0 * 8)), dim3(256), 0, n->stream, x, P0, n->cfg.cin,
+                     n->xin.p);
+  for (int l = 0; l < L; ++l) {
+    Img g{B, imgH(n, l), imgW(n, l)};
+    const int C = chans(n, l);
+    View<const bf16> in = l == 0 ? cv(n->xin) : cv(n->pool[l]);
+    int rc = conv_fwd(n, n->e1[l], g, in, mv(n->mid_e[l]));
+    if (rc) return rc;
+    View<bf16> eout = l < L - 1 ? mv(n->cat[l], C) : mv(n->bott);
+    rc = conv_fwd(n, n->e2[l], g, cv(n->mid_e[l]), eout);
+    if (rc) return rc;
+    if (l < L - 1) {
+      const int64_t cnt = (int64_t)B * (g.H / 2) * (g.W / 2) * C;
+      hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, g,
+                         View<const bf16>{eout.p, eout.cs, eout.coff}, C, mv(n->pool[l + 1]));
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    Img gl{B, imgH(n, l), imgW(n, l)}, gu{B, imgH(n, l + 1), imgW(n, l + 1)};
+    View<const bf16> uin = l == L - 2 ? cv(n->bott) : cv(n->dec[l + 1]);
+    int rc = up_fwd(n, n->up[l], gu, uin, mv(n->cat[l], 0));
+    if (rc) return rc;
+    rc = conv_fwd(n, n->d1[l], gl, cv(n->cat[l]), mv(n->mid_d[l]));
+    if (rc) return rc;
+    rc = conv_fwd(n, n->d2[l], gl, cv(n->mid_d[l]), mv(n->dec[l]));
+    if (rc) return rc;
+  }
+  Img g0{B, n->cfg.H, n->cfg.W};
+  int rc = conv_fwd_t<1, false, true>(n, n->head, g0, cv(n->dec[0]), View<bf16>{nullptr, 0, 0}, mv(n->y));
+  if (rc) return rc;
+  HTRY(hipGetLastError());
+  return WS_OK;
+}
+
+int backward(ws_net *n, int B) {
+  const int L = n->L;
+  Img g0{B, n->cfg.H, n->cfg.W};
+  int rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), View<const bf16>{nullptr, 0, 0}, cv(n->dy),
+                                mv(n->ddec[0]), 0);
+  if (rc) return rc;
+  for (int l = 0; l <= L - 2; ++l) {
+    Img gl{B, imgH(n, l), imgW(n, l)}, gu{B, imgH(n, l + 1), imgW(n, l + 1)};
+    rc = conv_bwd_t<3, true>(n, n->d2[l], gl, cv(n->mid_d[l]), cv(n->dec[l]), cv(n->ddec[l]), mv(n->dmid_d[l]), 0);
+    if (rc) return rc;
+    rc = conv_bwd_t<3, true>(n, n->d1[l], gl, cv(n->cat[l]), cv(n->mid_d[l]), cv(n->dmid_d[l]), mv(n->dcat[l]), 0);
+    if (rc) return rc;
+    View<const bf16> uin = l == L - 2 ? cv(n->bott) : cv(n->dec[l + 1]);
+    View<float> dup = l == L - 2 ? mv(n->dbott) : mv(n->ddec[l + 1]);
+    rc = up_bwd(n, n->up[l], gu, uin, cv(n->dcat[l], 0), dup);
+    if (rc) return rc;
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    Img g{B, imgH(n, l), imgW(n, l)};
+    const int C = chans(n, l);
+    View<const bf16> eout = l < L - 1 ? cv(n->cat[l], C) : cv(n->bott);
+    View<const float> deout = l < L - 1 ? cv(n->dcat[l], C) : cv(n->dbott);
+    rc = conv_bwd_t<3, true>(n, n->e2[l], g, cv(n->mid_e[l]), eout, deout, mv(n->dmid_e[l]), 0);
+    if (rc) return rc;
+    View<const bf16> in = l == 0 ? cv(n->xin) : cv(n->pool[l]);
+    View<float> din = l == 0 ? View<float>{nullptr, 0, 0} : mv(n->dpool[l]);
+    rc = conv_bwd_t<3, true>(n, n->e1[l], g, in, cv(n->mid_e[l]), cv(n->dmid_e[l]), din, 0);
+    if (rc) return rc;
+    if (l > 0) {  // route the pooled gradient into the level l-1 encoder output
+      Img gp{B, imgH(n, l - 1), imgW(n, l - 1)};
+      const int Cp = chans(n, l - 1);
+      const int64_t cnt = (int64_t)B * g.H * g.W * Cp;
+      hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, gp, cv(n->cat[l - 1], Cp), Cp,
+                         cv(n->dpool[l]), mv(n->dcat[l - 1], Cp));
+    }
+  }
+  HTRY(hipGetLastError());
+  return WS_OK;
+}
+
+int check_batch(const ws_net *n, int B) {
+  if (B < 1 || B > n->cfg.max_batch) return fail(WS_EINVAL, "batch %d outside 1..%d", B, n->cfg.max_batch);
+  return WS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
+  if (!c || !out) return fail(WS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (c->levels < 2 || c->levels > 6) return fail(WS_EINVAL, "levels must be 2..6");
+  if (c->base < 8 || c->base % 8) return fail(WS_EINVAL, "base channels must be a multiple of 8");
+  if (c->cin < 1 || c->cin > 8 || c->cout < 1 || c->cout > 8) return fail(WS_EINVAL, "cin, cout must be 1..8");
+  if (c->max_batch < 1) return fail(WS_EINVAL, "max_batch must be >= 1");
+  const int div = 1 << (c->levels - 1);
+  if (c->H % div || c->W % div) return fail(WS_EINVAL, "H and W must be divisible by 2^(levels-1)");
+  // the up-sampling GEMM keeps one output parity per 64-row tile
+  const int64_t Plow = (int64_t)(c->H / div) * (c->W / div);
+  if (Plow % 64) return fail(WS_EINVAL, "lowest level must hold a multiple of 64 pixels");
+  // element indices of the largest activation buffer ([up | skip] at level 0) are 32-bit
+  if ((int64_t)c->max_batch * c->H * c->W * std::max(2 * c->base, 8) >= (1LL << 31))
+    return fail(WS_EINVAL, "max_batch * H * W * 2 * base must stay below 2^31");
+  ws_net *n = new (std::nothrow) ws_net();
+  if (!n) return fail(WS_ENOMEM, "host allocation failed");
+  n->cfg = *c;
+  n->L = c->levels;
+  n->C0 = c->base;
+  n->stream = (hipStream_t)hip_stream;
+  const int L = n->L;
+  int64_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    const int C = chans(n, l), Cin = l == 0 ? 8 : chans(n, l - 1);
+    n->e1.push_back(make_conv(off, 3, Cin, C, true));
+    n->e2.push_back(make_conv(off, 3, C, C, true));
+  }
+  n->up.resize(L - 1);
+  n->d1.resize(L - 1);
+  n->d2.resize(L - 1);
+  for (int l = L - 2; l >= 0; --l) {
+    const int C = chans(n, l);
+    n->up[l] = make_up(off, chans(n, l + 1), C);
+    n->d1[l] = make_conv(off, 3, 2 * C, C, true);
+    n->d2[l] = make_conv(off, 3, C, C, true);
+  }
+  n->head = make_conv(off, 1, n->C0, 8, false);
+  n->np = off;
+  int rc = WS_OK;
+  rc = rc ? rc : dalloc(n, &n->params, n->np);
+  rc = rc ? rc : dalloc(n, &n->grads, n->np);
+  rc = rc ? rc : dalloc(n, &n->m, n->np);
+  rc = rc ? rc : dalloc(n, &n->v, n->np);
+  auto wcopies = [&](bf16 *&Wt, bf16 *&WtT, int64_t nw) {
+    if (!rc) rc = dalloc(n, &Wt, nw);
+    if (!rc) rc = dalloc(n, &WtT, nw);
+  };
+  for (auto &x : n->e1) wcopies(x.Wt, x.WtT, x.nw());
+  for (auto &x : n->e2) wcopies(x.Wt, x.WtT, x.nw());
+  for (auto &x : n->d1) wcopies(x.Wt, x.WtT, x.nw());
+  for (auto &x : n->d2) wcopies(x.Wt, x.WtT, x.nw());
+  for (auto &x : n->up) wcopies(x.Wt, x.WtT, x.nw());
+  wcopies(n->head.Wt, n->head.WtT, n->head.nw());
+  // activations and gradients
+  n->pool.resize(L);
+  n->dpool.resize(L);
+  n->mid_e.resize(L);
+  n->dmid_e.resize(L);
+  n->cat.resize(L);
+  n->dcat.resize(L);
+  n->mid_d.resize(L);
+  n->dmid_d.resize(L);
+  n->dec.resize(L);
+  n->ddec.resize(L);
+  if (!rc) rc = buf(n, n->xin, 0, 8);
+  for (int l = 0; l < L && !rc; ++l) {
+    const int C = chans(n, l);
+    if (l > 0) {
+      rc = buf(n, n->pool[l], l, chans(n, l - 1));
+      if (!rc) rc = buf(n, n->dpool[l], l, chans(n, l - 1));
+    }
+    if (!rc) rc = buf(n, n->mid_e[l], l, C);
+    if (!rc) rc = buf(n, n->dmid_e[l], l, C);
+    if (l < L - 1) {
+      if (!rc) rc = buf(n, n->cat[l], l, 2 * C);
+      if (!rc) rc = buf(n, n->dcat[l], l, 2 * C);
+      if (!rc) rc = buf(n, n->mid_d[l], l, C);
+      if (!rc) rc = buf(n, n->dmid_d[l], l, C);
+      if (!rc) rc = buf(n, n->dec[l], l, C);
+      if (!rc) rc = buf(n, n->ddec[l], l, C);
+    }
+  }
+  if (!rc) rc = buf(n, n->bott, L - 1, chans(n, L - 1));
+  if (!rc) rc = buf(n, n->dbott, L - 1, chans(n, L - 1));
+  if (!rc) rc = buf(n, n->y, 0, 8);
+  if (!rc) rc = buf(n, n->dy, 0, 8);
+  // split-K scratch: at most 1024/tiles splits of a weight-gradient matrix
+  size_t worst = 0;
+  auto need = [&](int M, int N) {
+    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    const int s = std::max(1, 1024 / std::max(tiles, 1));
+    worst = std::max(worst, (size_t)(s + 1) * M * N);
+  };
+  for (auto &x : n->e1) need(x.Cout, 9 * x.Cin + 1);
+  for (auto &x : n->e2) need(x.Cout, 9 * x.Cin + 1);
+  for (auto &x : n->d1) need(x.Cout, 9 * x.Cin + 1);
+  for (auto &x : n->d2) need(x.Cout, 9 * x.Cin + 1);
+  for (auto &x : n->up) need(4 * x.Cout, x.Cin + 1);
+  need(8, n->C0 + 1);
+  n->scratch_floats = worst;
+  if (!rc) rc = dalloc(n, &n->scratch, worst);
+  n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W * 8);
+  if (!rc) rc = dalloc(n, &n->loss_part, n->n_loss_blocks);
+  if (!rc) rc = dalloc(n, &n->loss, 1);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(n->stream);
+    if (e != hipSuccess) rc = fail(WS_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  if (rc) {
+    ws_destroy(n);
+    return rc;
+  }
+  *out = n;
+  return WS_OK;
+}
+
+void ws_destroy(ws_net *n) {
+  if (!n) return;
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
+  else (void)hipDeviceSynchronize();
+  for (void *p : n->allocs) (void)hipFree(p);
+  delete n;
+}
+
+int64_t ws_num_params(const ws_net *n) { return n ? n->np : -1; }
+int64_t ws_device_bytes(const ws_net *n) { return n ? n->bytes : -1; }
+
+int ws_set_params(ws_net *n, const float *host, int64_t count) {
+  if (!n || !host) return fail(WS_EINVAL, "NULL argument");
+  if (count != n->np) return fail(WS_EINVAL, "expected %lld parameters", (long long)n->np);
+  HTRY(hipMemcpyAsync(n->params, host, sizeof(float) * count, hipMemcpyHostToDevice, n->stream));
+  HTRY(hipMemsetAsync(n->m, 0, sizeof(float) * count, n->stream));
+  HTRY(hipMemsetAsync(n->v, 0, sizeof(float) * count, n->stream));
+  n->adam_t = 0;
+  int rc = refresh_weights(n);
+  if (rc) return rc;
+  HTRY(hipStreamSynchronize(n->stream));
+  return WS_OK;
+}
+
+int ws_get_params(ws_net *n, float *host, int64_t count) {
+  if (!n || !host || count != n->np) return fail(WS_EINVAL, "bad arguments");
+  HTRY(hipMemcpyAsync(host, n->params, sizeof(float) * count, hipMemcpyDeviceToHost, n->stream));
+  HTRY(hipStreamSynchronize(n->stream));
+  return WS_OK;
+}
+
+int ws_get_grads(ws_net *n, float *host, int64_t count) {
+  if (!n || !host || count != n->np) return fail(WS_EINVAL, "bad arguments");
+  HTRY(hipMemcpyAsync(host, n->grads, sizeof(float) * count, hipMemcpyDeviceToHost, n->stream));
+  HTRY(hipStreamSynchronize(n->stream));
+  return WS_OK;
+}
+
+int ws_forward(ws_net *n, const float *x, int32_t batch, float *y) {
+  if (!n || !x || !y) return fail(WS_EINVAL, "NULL argument");
+  int rc = check_batch(n, batch);
+  if (rc) return rc;
+  rc = forward(n, x, batch);
+  if (rc) return rc;
+  const int P = batch * n->cfg.H * n->cfg.W;
+  hipLaunchKernelGGL(k_unpack_output, dim3(blocks((int64_t)P * n->cfg.cout)), dim3(256), 0, n->stream, n->y.p, 8, P,
+                     n->cfg.cout, y);
+  HTRY(hipGetLastError());
+  return WS_OK;
+}
+
+int ws_backward(ws_net *n, const float *x, const float *target, int32_t batch, double *loss) {
+  if (!n || !x || !target) return fail(WS_EINVAL, "NULL argument");
+  int rc = check_batch(n, batch);
+  if (rc) return rc;
+  rc = forward(n, x, batch);
+  if (rc) return rc;
+  const int P = batch * n->cfg.H * n->cfg.W;
+  const int nb = (int)blocks((int64_t)P * 8);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, n->stream, n->y.p, 8, target, P, n->cfg.cout, n->dy.p,
+                     n->loss_part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, n->stream, n->loss_part, nb,
+                     1.0 / ((double)P * n->cfg.cout), n->loss);
+  rc = backward(n, batch);
+  if (rc) return rc;
+  if (loss) {
+    HTRY(hipMemcpyAsync(loss, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+    HTRY(hipStreamSynchronize(n->stream));
+  }
+  return WS_OK;
+}
+
+int ws_adam(ws_net *n, float lr, float beta1, float beta2, float eps, float weight_decay) {
+  if (!n) return fail(WS_EINVAL, "NULL network");
+  n->adam_t += 1;
+  const float c1 = 1.f - powf(beta1, (float)n->adam_t), c2 = 1.f - powf(beta2, (float)n->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3(blocks(n->np)), dim3(256), 0, n->stream, n->params, n->grads, n->m, n->v, n->np, lr,
+                     beta1, beta2, eps, c1, c2, weight_decay);
+  HTRY(hipGetLastError());
+  return refresh_weights(n);
+}
+
+int ws_train_step(ws_net *n, const float *x, const float *target, int32_t batch, float lr, double *loss) {
+  int rc = ws_backward(n, x, target, batch, loss);
+  if (rc) return rc;
+  return ws_adam(n, lr, 0.9f, 0.999f, 1e-8f, 0.f);
+}
+
+int ws_flops(const ws_net *n, int32_t batch, double *fwd, double *bwd) {
+  if (!n) return fail(WS_EINVAL, "NULL network");
+  double f = 0;
+  for (int l = 0; l < n->L; ++l) {
+    const double P = (double)batch * imgH(n, l) * imgW(n, l);
+    auto conv = [&](const Conv &c) { f += 2.0 * P * c.Cout * c.KS * c.KS * c.Cin; };
+    conv(n->e1[l]);
+    conv(n->e2[l]);
+    if (l < n->L - 1) {
+      conv(n->d1[l]);
+      conv(n->d2[l]);
+      f += 2.0 * P * n->up[l].Cout * n->up[l].Cin;  // each output pixel: Cin MACs per channel
+    }
+  }
+  f += 2.0 * batch * n->cfg.H * n->cfg.W * 8 * n->C0;
+  if (fwd) *fwd = f;
+  if (bwd) *bwd = 2.0 * f;
+  return WS_OK;
+}
+
+int ws_malloc(int64_t bytes, void **p) {
+  if (!p || bytes < 0) return fail(WS_EINVAL, "bad arguments");
+  hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+  if (e != hipSuccess) return fail(WS_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
+  return WS_OK;
+}
+
+int ws_free(void *p) {
+  HTRY(hipFree(p));
+  return WS_OK;
+}
+
+int ws_memcpy(void *dst, const void *src, int64_t bytes, int32_t kind) {
+  if (bytes < 0) return fail(WS_EINVAL, "negative size");
+  if (kind < 0 || kind > 2) return fail(WS_EINVAL, "copy kind must be 0, 1 or 2");
+  const hipMemcpyKind k = kind == 0 ? hipMemcpyHostToDevice : kind == 1 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  HTRY(hipDeviceSynchronize());  // after work queued on any stream
+  HTRY(hipMemcpy(dst, src, bytes, k));
+  return WS_OK;
+}
+
+int ws_sync(void) {
+  HTRY(hipDeviceSynchronize());
+  return WS_OK;
+}
+
+const char *ws_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
