@@ -15,7 +15,6 @@ timed on the host cores over a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import re
@@ -45,15 +44,6 @@ def main_kernel_bytes(dim: int, storage: str) -> int:
     return (pops + 2 * r_b) + (pops + r_b + 4 * dim)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2003_11069_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hpp", ".hip")) and f.startswith("lb_"):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profile(name: str):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
     when absent or taken on a different kernel source."""
@@ -63,6 +53,7 @@ def traffic_from_profile(name: str):
     txt = open(path).read()
     m = re.search(r"kernel_source_sha256:\s*(\w+)", txt)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    from paper_2003_11069_amd.profile_summary import kernel_source_hash
     if not m or not t or m.group(1) != kernel_source_hash():
         return None
     return float(t.group(1))
@@ -96,7 +87,8 @@ def main(argv=None):
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp32_f32"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep"])
+    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep", "unet"])
+    ap.add_argument("--batch", type=int, default=16, help="U-Net training batch (--workload unet)")
     ap.add_argument("--mode", default="persistent", choices=["persistent", "launch"])
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -111,6 +103,8 @@ def main(argv=None):
 
     if a.workload == "sweep":
         return bench_sweep(a)
+    if a.workload == "unet":
+        return bench_unet(a)
     case = synth.hex_channel_3d()
     prm = case.params
     dim = 3
@@ -195,6 +189,41 @@ def bench_sweep(a):
                       "graphs": b.graphs},
            "step_bytes_per_node_measured_layout": bytes_node,
            "achieved_GBps_step": round(bytes_node * mlups * 1e6 / 1e9, 1)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_unet(a):
+    """Training step of the warm-start U-Net (4 levels, 32 base channels,
+    3 x 128 x 256 inputs and targets, batch --batch): forward, MSE, backward
+    and Adam on BF16 MFMA kernels.  Prints one JSON line with the training
+    throughput in TFLOP/s (2 FLOP per multiply-add of the convolutions)
+    against the dense BF16 MFMA peak."""
+    import synth
+    from paper_2003_11069_amd import ws
+    B, Hh, Ww = a.batch, 128, 256
+    net = ws.UNet(ws.UNetConfig(levels=4, base=32, cin=3, cout=3, H=Hh, W=Ww, max_batch=B))
+    net.set_params(synth.unet_params(4, 32, seed=1))
+    x, t = synth.unet_batch(B, Hh, Ww, 3, 3, seed=2)
+    dx, dt = ws.DeviceArray.from_host(x), ws.DeviceArray.from_host(t)
+    fwd, bwd = net.flops(B)
+    for _ in range(a.warmup):
+        net.train_step_ptr(dx.ptr(), dt.ptr(), B, 1e-4)
+    ws.sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        net.train_step_ptr(dx.ptr(), dt.ptr(), B, 1e-4)
+    ws.sync()
+    el = time.perf_counter() - t0
+    tflops = (fwd + bwd) * a.steps / el / 1e12
+    out = {"metric": "U-Net training throughput (warm start)", "value": round(B * a.steps / el, 1),
+           "unit": "samples/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": round(el / a.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic (seeded smooth fields)",
+           "config": {"workload": "U-Net 4 levels, base 32, 3x128x256 -> 3x128x256, MSE + Adam",
+                      "batch": B, "params": net.n_params, "gflop_per_sample_fwd": round(fwd / B / 1e9, 3)},
+           "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": round(tflops / 2500.0, 4), "traffic": None}}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -189,6 +189,25 @@ __device__ __forceinline__ Offs make_offs(int nx, int ny, int nz, int walls, int
   return o;
 }
 
+// Stores of k_main's outputs, optionally non-temporal (streamed past the
+// caches): LBNCI_NT = 0 none, 1 the populations, 2 also the colour scalars.
+#ifndef LBNCI_NT
+#define LBNCI_NT 0
+#endif
+template <int LEVEL, typename T>
+__device__ __forceinline__ void stb_out(T *base, uint32_t byte_off, T v) {
+  char *p = reinterpret_cast<char *>(base) + (size_t)byte_off;
+  if constexpr (LBNCI_NT >= LEVEL) {
+    if constexpr (sizeof(T) == 2) {
+      __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t *>(p));
+    } else {
+      __builtin_nontemporal_store(v, reinterpret_cast<T *>(p));
+    }
+  } else {
+    *reinterpret_cast<T *>(p) = v;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T ldb(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (size_t)byte_off);
@@ -575,8 +594,8 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         const float sn_i = omc * f[i] + C + O;
         const float sn_o = omc * f[io] + C - O;
         const S q_i = from_f<S>(sn_i), q_o = from_f<S>(sn_o);
-        stb(A.out.s, nb + (uint32_t)i * NB, q_i);
-        stb(A.out.s, nb + (uint32_t)io * NB, q_o);
+        stb_out<1>(A.out.s, nb + (uint32_t)i * NB, q_i);
+        stb_out<1>(A.out.s, nb + (uint32_t)io * NB, q_o);
         // populations heading into a wall: reflected copy into the wall row,
         // node x + c_d, slot opp(d) (direction i has c_y = icy, opp(i) -icy)
         auto ghost = [&](int d, int dcx, int dcy, int dcz, S q) {
@@ -584,21 +603,21 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
           const int zw = (D == 3) ? wrapi(z + dcz, A.nz) : 0;
           const uint32_t nw =
               (uint32_t)xw + (uint32_t)A.nx * ((uint32_t)(y + dcy) + (uint32_t)A.ny * zw);
-          stb(A.out.s, nw * (uint32_t)sizeof(S) + (uint32_t)L::opp(d) * NB, q);
+          stb_out<1>(A.out.s, nw * (uint32_t)sizeof(S) + (uint32_t)L::opp(d) * NB, q);
         };
         if ((icy == -1 && low) || (icy == 1 && high)) ghost(i, icx, icy, icz, q_i);
         if ((icy == 1 && low) || (icy == -1 && high)) ghost(io, -icx, -icy, -icz, q_o);
         sum_q += (R)L::w(i) * ((R)to_f(q_i) + (R)to_f(q_o));
       }
       const float srest = (float)((dr - sum_q) * (R)(1.0 / L::w(L::REST)));
-      if (is_fp32<S>::value) stb(A.out.s, nb + (uint32_t)L::REST * NB, from_f<S>(srest));
-      else st(A.out.s0, n, srest);
+      if (is_fp32<S>::value) stb_out<1>(A.out.s, nb + (uint32_t)L::REST * NB, from_f<S>(srest));
+      else stb_out<1>(A.out.s0, n * 4u, srest);
       const R dr_t = sum_q + (R)L::w(L::REST) * (R)srest;
-      st(A.out.a, n, r1 / ((R)1 + dr_t));
+      stb_out<2>(A.out.a, n * (uint32_t)sizeof(R), r1 / ((R)1 + dr_t));
       const R b = A.beta * r1 * (rho - r1) * irho;
-      st(A.out.B, n, (float)(b * Gh[0]));
-      st(A.out.B + A.N, n, (float)(b * Gh[1]));
-      if (D == 3) st(A.out.B + 2 * (size_t)A.N, n, (float)(b * Gh[2]));
+      stb_out<2>(A.out.B, n * 4u, (float)(b * Gh[0]));
+      stb_out<2>(A.out.B + A.N, n * 4u, (float)(b * Gh[1]));
+      if (D == 3) stb_out<2>(A.out.B + 2 * (size_t)A.N, n * 4u, (float)(b * Gh[2]));
     }
   }
 
