@@ -20,14 +20,31 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f4;
 typedef __bf16 bf16;
 
-constexpr int BM = 64, BN = 64, BK = 32;  // block tile (M x N), K step
-constexpr int LDK = BK + 8;               // LDS row stride (bf16), 80 bytes
+constexpr int BK = 32;       // K step of the GEMM engine
+constexpr int LDK = BK + 8;  // LDS row stride (bf16), 80 bytes
 
 __device__ __forceinline__ bf16x8 zero8() {
   bf16x8 z;
   for (int j = 0; j < 8; ++j) z[j] = (bf16)0.f;
   return z;
 }
+
+// Exact unsigned division n / d for n < 2^31 by multiply and shift
+// (Granlund & Montgomery, PLDI 1994): m = ceil(2^(31+l) / d), l = ceil(log2 d),
+// q = (n m) >> (31 + l).  Built on the host.
+struct Div {
+  uint32_t d, m, s;
+  static Div make(uint32_t d) {
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    Div r;
+    r.d = d;
+    r.m = (uint32_t)(((1ull << (31 + l)) + d - 1) / d);
+    r.s = 31u + (uint32_t)l;
+    return r;
+  }
+  __device__ __forceinline__ uint32_t q(uint32_t n) const { return (uint32_t)(((uint64_t)n * m) >> s); }
+};
 
 // NHWC tensor view: element (pixel p, channel c) at p*cs + coff + c.
 template <typename T>
@@ -36,61 +53,157 @@ struct View {
   int cs, coff;
 };
 
+// Image batch geometry with the divisions used to split a pixel index.
 struct Img {
   int B, H, W;
+  Div dH, dW;
+  static Img make(int B, int H, int W) { return Img{B, H, W, Div::make(H), Div::make(W)}; }
   __device__ __forceinline__ int P() const { return B * H * W; }
+  __device__ __forceinline__ void split(int m, int &b, int &y, int &x) const {
+    const uint32_t t = dW.q((uint32_t)m);
+    x = m - (int)t * W;
+    b = (int)dH.q(t);
+    y = (int)t - b * H;
+  }
 };
 
 // ---------------------------------------------------------------------------
-// GEMM engine: C[M,N] = sum_k A[m,k] B[k,n].  The problem fills the LDS tiles
-// As[64][LDK] (row m, k contiguous) and Bs[64][LDK] (column n, k contiguous)
-// for the tile (m0, n0, k0) and consumes the accumulators in store().  K may
-// be split over gridDim.z (problem decides the range of each split).
-template <class P>
+// GEMM engine: C[M,N] = sum_k A[m,k] B[k,n] on v_mfma_f32_16x16x32_bf16.
+// Block tile BM x BN (BM in {64,128}, BN in {32,64,128}), 4 waves in 2 x 2,
+// each (BM/2) x (BN/2) of 16 x 16 MFMA tiles; K in steps of 32 through two
+// LDS buffers, the next step's global loads issued before the current step's
+// MFMAs (one barrier per step).  The problem supplies 8-element operand
+// chunks -- ROW: 8 consecutive k of one row; COL: 8 consecutive rows at one
+// k, gathered for 4 consecutive k and stored transposed into LDS as 8-byte
+// rows -- and consumes the accumulators in store().  K may be split over
+// gridDim.z (the problem decides each split's range).
+enum { ROW = 0, COL = 1 };
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+
+template <int LAYOUT, int R>
+struct ChunkMap {
+  static constexpr int N = LAYOUT == ROW ? R * BK / 8 : R * BK / 32;  // chunks per tile
+  static constexpr int V = LAYOUT == ROW ? 1 : 4;                     // bf16x8 per chunk
+  __device__ __forceinline__ static void at(int q, int &row, int &k) {
+    if (LAYOUT == ROW) {
+      row = q >> 2;
+      k = (q & 3) * 8;
+    } else {
+      row = (q % (R / 8)) * 8;
+      k = (q / (R / 8)) * 4;
+    }
+  }
+};
+
+// Stores one chunk (V vectors starting at v) into an LDS tile.
+template <int LAYOUT>
+__device__ __forceinline__ void put_chunk(bf16 (*S)[LDK], int row, int k, const bf16x8 *v) {
+  if (LAYOUT == ROW) {
+    *reinterpret_cast<bf16x8 *>(&S[row][k]) = v[0];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      bf16x4 w;
+      w[0] = v[0][j];
+      w[1] = v[1][j];
+      w[2] = v[2][j];
+      w[3] = v[3][j];
+      *reinterpret_cast<bf16x4 *>(&S[row + j][k]) = w;
+    }
+  }
+}
+
+template <class P, int BM_, int BN_>
 __global__ __launch_bounds__(256) void k_gemm(P prob) {
-  __shared__ __attribute__((aligned(16))) bf16 As[BM][LDK];
-  __shared__ __attribute__((aligned(16))) bf16 Bs[BN][LDK];
+  constexpr int WM = BM_ / 2, WN = BN_ / 2, TM = WM / 16, TN = WN / 16;
+  using MA = ChunkMap<P::A_LAYOUT, BM_>;
+  using MB = ChunkMap<P::B_LAYOUT, BN_>;
+  constexpr int CA = (MA::N + 255) / 256, CB = (MB::N + 255) / 256;
+  __shared__ __attribute__((aligned(16))) bf16 As[2][BM_][LDK];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN_][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int m0 = blockIdx.x * BM_, n0 = blockIdx.y * BN_;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   int kbeg, kend;
   prob.krange(blockIdx.z, kbeg, kend);
-  f4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    prob.fill_a(As, m0, k0, kend, tid);
-    prob.fill_b(Bs, n0, k0, kend, tid);
-    __syncthreads();
-    const int r = lane & 15, kq = 8 * (lane >> 4);
-    bf16x8 a[2], b[2];
-    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + r][kq]);
-    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * j + r][kq]);
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  constexpr int VA = MA::V, VB = MB::V;
+  bf16x8 ra[CA * VA], rb[CB * VB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < CA; ++c) {
+      const int q = tid + 256 * c;
+      int row, k;
+      MA::at(q, row, k);
+      if (q < MA::N) {
+#pragma unroll
+        for (int t = 0; t < VA; ++t) ra[c * VA + t] = prob.a(m0 + row, k0 + k + t, kend, m0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int q = tid + 256 * c;
+      int row, k;
+      MB::at(q, row, k);
+      if (q < MB::N) {
+#pragma unroll
+        for (int t = 0; t < VB; ++t) rb[c * VB + t] = prob.b(n0 + row, k0 + k + t, kend, m0);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < CA; ++c) {
+      const int q = tid + 256 * c;
+      int row, k;
+      MA::at(q, row, k);
+      if (q < MA::N) put_chunk<P::A_LAYOUT>(As[buf], row, k, &ra[c * VA]);
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int q = tid + 256 * c;
+      int row, k;
+      MB::at(q, row, k);
+      if (q < MB::N) put_chunk<P::B_LAYOUT>(Bs[buf], row, k, &rb[c * VB]);
+    }
+  };
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+  __syncthreads();
+  int buf = 0;
+  const int r = lane & 15, kq = 8 * (lane >> 4);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
+    bf16x8 a[TM], b[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][wm + 16 * i + r][kq]);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn + 16 * j + r][kq]);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
         const int n = n0 + wn + 16 * j + (lane & 15);
         prob.store(m, n, acc[i][j][q], blockIdx.z);
       }
-}
-
-// Default tile fill: each of 256 threads writes 8 consecutive k of one row,
-// obtained from row8(row, k) (zero beyond the matrix).
-template <bool IS_A, class P>
-__device__ __forceinline__ void fill_rows(const P &p, bf16 (*S)[LDK], int r0, int k0, int kend, int tid) {
-  const int row = tid >> 2, kq = (tid & 3) * 8;
-  const int k = k0 + kq;
-  bf16x8 v = zero8();
-  if (k < kend) {
-    if constexpr (IS_A) v = p.a8(r0 + row, k);
-    else v = p.b8(r0 + row, k);
-  }
-  *reinterpret_cast<bf16x8 *>(&S[row][kq]) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -99,33 +212,30 @@ __device__ __forceinline__ void fill_rows(const P &p, bf16 (*S)[LDK], int r0, in
 // M = pixels, N = Cout, K = KS*KS*Cin (Cin multiple of 8).
 template <int KS, bool RELU, bool OUT_F32>
 struct ConvFwd {
+  static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
   Img g;
   View<const bf16> in;
   int Cin, Cout;
+  Div dCin;
   const bf16 *Wt;   // [Cout][K]
   const float *bias;
   View<bf16> out;      // BF16 output (OUT_F32 = false)
   View<float> outf;    // FP32 output (OUT_F32 = true)
   __device__ __forceinline__ int K() const { return KS * KS * Cin; }
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = K(); }
-  __device__ __forceinline__ bf16x8 a8(int m, int k) const {
-    if (m >= g.P()) return zero8();
-    const int tap = k / Cin, ci = k - tap * Cin;
-    const int x = m % g.W, t = m / g.W, y = t % g.H, b = t / g.H;
+  __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
+    if (m >= g.P() || k >= kend) return zero8();
+    const int tap = (int)dCin.q((uint32_t)k), ci = k - tap * Cin;
+    int b, y, x;
+    g.split(m, b, y, x);
     const int yy = y + tap / KS - KS / 2, xx = x + tap % KS - KS / 2;
     if (yy < 0 || yy >= g.H || xx < 0 || xx >= g.W) return zero8();
     const int q = (b * g.H + yy) * g.W + xx;
     return *reinterpret_cast<const bf16x8 *>(in.p + (size_t)q * in.cs + in.coff + ci);
   }
-  __device__ __forceinline__ bf16x8 b8(int n, int k) const {
-    if (n >= Cout) return zero8();
+  __device__ __forceinline__ bf16x8 b(int n, int k, int kend, int) const {
+    if (n >= Cout || k >= kend) return zero8();
     return *reinterpret_cast<const bf16x8 *>(Wt + (size_t)n * K() + k);
-  }
-  __device__ __forceinline__ void fill_a(bf16 (*S)[LDK], int m0, int k0, int ke, int tid) const {
-    fill_rows<true>(*this, S, m0, k0, ke, tid);
-  }
-  __device__ __forceinline__ void fill_b(bf16 (*S)[LDK], int n0, int k0, int ke, int tid) const {
-    fill_rows<false>(*this, S, n0, k0, ke, tid);
   }
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     if (m >= g.P() || n >= Cout) return;
@@ -140,15 +250,19 @@ struct ConvFwd {
 // forward output (act > 0), rounded to BF16 for the MFMA.
 template <bool RELU>
 __device__ __forceinline__ bf16x8 grad8(const View<const float> &d, const View<const bf16> &act, int q, int c) {
-  const float *s = d.p + (size_t)q * d.cs + d.coff + c;
-  bf16x8 v;
+  const float4 *s = reinterpret_cast<const float4 *>(d.p + (size_t)q * d.cs + d.coff + c);
+  const float4 lo = s[0], hi = s[1];
+  const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  bf16x8 r;
   if (RELU) {
     const bf16x8 a = *reinterpret_cast<const bf16x8 *>(act.p + (size_t)q * act.cs + act.coff + c);
-    for (int j = 0; j < 8; ++j) v[j] = (bf16)((float)a[j] > 0.f ? s[j] : 0.f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = (bf16)((float)a[j] > 0.f ? v[j] : 0.f);
   } else {
-    for (int j = 0; j < 8; ++j) v[j] = (bf16)s[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = (bf16)v[j];
   }
-  return v;
+  return r;
 }
 
 // Backward-data of ConvFwd: dIn[p, ci] = sum_{ky,kx,co} WtT[ci][(ky*KS+kx)*Cout + co]
@@ -156,32 +270,29 @@ __device__ __forceinline__ bf16x8 grad8(const View<const float> &d, const View<c
 // M = pixels, N = Cin, K = KS*KS*Cout (Cout multiple of 8).  Writes or adds FP32.
 template <int KS, bool RELU>
 struct ConvBwdData {
+  static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
   Img g;
   View<const float> dout;
   View<const bf16> act;  // forward output (ReLU mask)
   int Cin, Cout;
+  Div dCout;
   const bf16 *WtT;  // [Cin][K]
   View<float> din;
   int accumulate;
   __device__ __forceinline__ int K() const { return KS * KS * Cout; }
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = K(); }
-  __device__ __forceinline__ bf16x8 a8(int m, int k) const {
-    if (m >= g.P()) return zero8();
-    const int tap = k / Cout, co = k - tap * Cout;
-    const int x = m % g.W, t = m / g.W, y = t % g.H, b = t / g.H;
+  __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
+    if (m >= g.P() || k >= kend) return zero8();
+    const int tap = (int)dCout.q((uint32_t)k), co = k - tap * Cout;
+    int b, y, x;
+    g.split(m, b, y, x);
     const int yy = y + tap / KS - KS / 2, xx = x + tap % KS - KS / 2;
     if (yy < 0 || yy >= g.H || xx < 0 || xx >= g.W) return zero8();
     return grad8<RELU>(dout, act, (b * g.H + yy) * g.W + xx, co);
   }
-  __device__ __forceinline__ bf16x8 b8(int n, int k) const {
-    if (n >= Cin) return zero8();
+  __device__ __forceinline__ bf16x8 b(int n, int k, int kend, int) const {
+    if (n >= Cin || k >= kend) return zero8();
     return *reinterpret_cast<const bf16x8 *>(WtT + (size_t)n * K() + k);
-  }
-  __device__ __forceinline__ void fill_a(bf16 (*S)[LDK], int m0, int k0, int ke, int tid) const {
-    fill_rows<true>(*this, S, m0, k0, ke, tid);
-  }
-  __device__ __forceinline__ void fill_b(bf16 (*S)[LDK], int n0, int k0, int ke, int tid) const {
-    fill_rows<false>(*this, S, n0, k0, ke, tid);
   }
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     if (m >= g.P() || n >= Cin) return;
@@ -192,17 +303,19 @@ struct ConvBwdData {
 
 // Backward-weight of ConvFwd, split over pixels:
 //   dW[co][k] = sum_p dPre[p, co] im2col(in)[p, k],  db[co] = sum_p dPre[p, co]
-// (the bias is column k = K of a ones column).  M = Cout, N = K + 1, reduction
-// over pixels; split z writes partial[z][m][n] (FP32), summed in fixed order by
-// k_split_reduce.  Tiles are filled transposed through LDS: each thread loads
-// 8 consecutive channels of one pixel.
-template <int KS, bool RELU>
+// (the bias is column k = K of a ones column).  Reduction over pixels; split z
+// writes partial[z][co][k] (FP32), summed in fixed order by k_split_reduce.
+// Both operands are COL chunks (8 channels of one pixel).  TR = false: M =
+// Cout, N = K + 1; TR = true (narrow Cout): M = K + 1, N = Cout.
+template <int KS, bool RELU, bool TR = false>
 struct ConvBwdWeight {
+  static constexpr int A_LAYOUT = COL, B_LAYOUT = COL;
   Img g;
   View<const float> dout;
   View<const bf16> act;
   View<const bf16> in;
   int Cin, Cout;
+  Div dCin;
   int chunk;          // pixels per split (multiple of BK)
   float *partial;     // [splits][Cout][K+1]
   __device__ __forceinline__ int Kw() const { return KS * KS * Cin; }
@@ -210,104 +323,105 @@ struct ConvBwdWeight {
     b = z * chunk;
     e = min(g.P(), b + chunk);
   }
-  __device__ __forceinline__ void fill_a(bf16 (*S)[LDK], int m0, int k0, int ke, int tid) const {
-    const int pl = tid >> 3, cl = (tid & 7) * 8;  // 32 pixels x 64 channels
-    const int p = k0 + pl, co = m0 + cl;
-    bf16x8 v = (p < ke && co < Cout) ? grad8<RELU>(dout, act, p, co) : zero8();
-    for (int j = 0; j < 8; ++j) S[cl + j][pl] = v[j];
+  __device__ __forceinline__ bf16x8 dpre(int co, int p, int kend) const {
+    return (p < kend && co < Cout) ? grad8<RELU>(dout, act, p, co) : zero8();
   }
-  __device__ __forceinline__ void fill_b(bf16 (*S)[LDK], int n0, int k0, int ke, int tid) const {
-    const int pl = tid >> 3, nl = (tid & 7) * 8;
-    const int p = k0 + pl, n = n0 + nl;
+  __device__ __forceinline__ bf16x8 col(int n, int p, int kend) const {
     bf16x8 v = zero8();
-    if (p < ke) {
-      if (n < Kw()) {
-        const int tap = n / Cin, ci = n - tap * Cin;
-        const int x = p % g.W, t = p / g.W, y = t % g.H, b = t / g.H;
-        const int yy = y + tap / KS - KS / 2, xx = x + tap % KS - KS / 2;
-        if (yy >= 0 && yy < g.H && xx >= 0 && xx < g.W)
-          v = *reinterpret_cast<const bf16x8 *>(in.p + (size_t)((b * g.H + yy) * g.W + xx) * in.cs + in.coff + ci);
-      } else if (n == Kw()) {
-        v[0] = (bf16)1.f;
-      }
+    if (p >= kend) return v;
+    if (n < Kw()) {
+      const int tap = (int)dCin.q((uint32_t)n), ci = n - tap * Cin;
+      int b, y, x;
+      g.split(p, b, y, x);
+      const int yy = y + tap / KS - KS / 2, xx = x + tap % KS - KS / 2;
+      if (yy >= 0 && yy < g.H && xx >= 0 && xx < g.W)
+        v = *reinterpret_cast<const bf16x8 *>(in.p + (size_t)((b * g.H + yy) * g.W + xx) * in.cs + in.coff + ci);
+    } else if (n == Kw()) {
+      v[0] = (bf16)1.f;
     }
-    for (int j = 0; j < 8; ++j) S[nl + j][pl] = v[j];
+    return v;
   }
+  __device__ __forceinline__ bf16x8 a(int m, int p, int kend, int) const { return TR ? col(m, p, kend) : dpre(m, p, kend); }
+  __device__ __forceinline__ bf16x8 b(int n, int p, int kend, int) const { return TR ? dpre(n, p, kend) : col(n, p, kend); }
   __device__ __forceinline__ void store(int m, int n, float v, int z) const {
-    if (m >= Cout || n > Kw()) return;
-    partial[((size_t)z * Cout + m) * (Kw() + 1) + n] = v;
+    const int co = TR ? n : m, k = TR ? m : n;
+    if (co >= Cout || k > Kw()) return;
+    partial[((size_t)z * Cout + co) * (Kw() + 1) + k] = v;
   }
 };
 
 // ---------------------------------------------------------------------------
 // 2x2 stride-2 transposed convolution (up-sampling), forward:
 //   out[(b, 2y+dy, 2x+dx), co] = sum_ci W[d][co][ci] in[(b,y,x), ci] + b[co], d = 2dy+dx.
-// Rows are ordered parity-major, m = d*Pin + p, so a 64-row tile has one
-// parity (Pin is a multiple of 64).  M = 4 Pin, N = Cout, K = Cin.
+// Rows are ordered parity-major, m = d*Pin + p, so a block tile has one
+// parity (Pin is a multiple of the tile height).  M = 4 Pin, N = Cout, K = Cin.
 struct UpFwd {
+  static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
   Img g;  // input image
   View<const bf16> in;
   int Cin, Cout;
+  Div dPin;
   const bf16 *Wt;  // [4][Cout][Cin]
   const float *bias;
   View<bf16> out;  // output image (2H x 2W)
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = Cin; }
-  __device__ __forceinline__ bf16x8 a8(int m, int k) const {
+  __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
     const int Pin = g.P();
-    if (m >= 4 * Pin) return zero8();
-    const int p = m % Pin;
+    if (m >= 4 * Pin || k >= kend) return zero8();
+    const int p = m - (int)dPin.q((uint32_t)m) * Pin;
     return *reinterpret_cast<const bf16x8 *>(in.p + (size_t)p * in.cs + in.coff + k);
   }
-  __device__ __forceinline__ void fill_a(bf16 (*S)[LDK], int m0, int k0, int ke, int tid) const {
-    fill_rows<true>(*this, S, m0, k0, ke, tid);
-  }
-  __device__ __forceinline__ void fill_b(bf16 (*S)[LDK], int n0, int k0, int ke, int tid) const {
-    const int row = tid >> 2, kq = (tid & 3) * 8;
-    const int d = (blockIdx.x * BM) / g.P();
-    const int n = n0 + row, k = k0 + kq;
-    bf16x8 v = (n < Cout && k < ke) ? *reinterpret_cast<const bf16x8 *>(Wt + ((size_t)d * Cout + n) * Cin + k)
-                                    : zero8();
-    *reinterpret_cast<bf16x8 *>(&S[row][kq]) = v;
+  __device__ __forceinline__ bf16x8 b(int n, int k, int kend, int m0) const {
+    if (n >= Cout || k >= kend) return zero8();
+    const int d = (int)dPin.q((uint32_t)m0);
+    return *reinterpret_cast<const bf16x8 *>(Wt + ((size_t)d * Cout + n) * Cin + k);
   }
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     const int Pin = g.P();
     if (m >= 4 * Pin || n >= Cout) return;
-    const int d = m / Pin, p = m % Pin;
-    const int x = p % g.W, t = p / g.W, y = t % g.H, b = t / g.H;
+    const int d = (int)dPin.q((uint32_t)m), p = m - d * Pin;
+    int b, y, x;
+    g.split(p, b, y, x);
     const int Y = 2 * y + (d >> 1), X = 2 * x + (d & 1);
     const size_t q = ((size_t)b * 2 * g.H + Y) * 2 * g.W + X;
     out.p[q * out.cs + out.coff + n] = (bf16)(v + bias[n]);
   }
 };
 
-// Backward-data of UpFwd: dIn[p, ci] = sum_{d,co} WT[ci][d*Cout + co] dOut[up(p,d), co].
+// Output-pixel index of input pixel p under up-sampling parity d.
+__device__ __forceinline__ int up_pixel(const Img &g, int p, int d) {
+  int b, y, x;
+  g.split(p, b, y, x);
+  return (b * 2 * g.H + 2 * y + (d >> 1)) * 2 * g.W + 2 * x + (d & 1);
+}
+
+__device__ __forceinline__ bf16x8 f32x8_to_bf16(const float *s) {
+  const float4 lo = reinterpret_cast<const float4 *>(s)[0], hi = reinterpret_cast<const float4 *>(s)[1];
+  bf16x8 v;
+  v[0] = (bf16)lo.x; v[1] = (bf16)lo.y; v[2] = (bf16)lo.z; v[3] = (bf16)lo.w;
+  v[4] = (bf16)hi.x; v[5] = (bf16)hi.y; v[6] = (bf16)hi.z; v[7] = (bf16)hi.w;
+  return v;
+}
+
+// Backward-data of UpFwd: dIn[p, ci] = sum_{d,co} WtT[ci][d*Cout + co] dOut[up(p,d), co].
 // M = Pin, N = Cin, K = 4 Cout.  No activation on the up-sampling output.
 struct UpBwdData {
+  static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
   Img g;
   View<const float> dout;  // output-image gradient
   int Cin, Cout;
+  Div dCout;
   const bf16 *WtT;  // [Cin][4][Cout]
   View<float> din;
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = 4 * Cout; }
-  __device__ __forceinline__ bf16x8 a8(int m, int k) const {
-    if (m >= g.P()) return zero8();
-    const int d = k / Cout, co = k - d * Cout;
-    const int x = m % g.W, t = m / g.W, y = t % g.H, b = t / g.H;
-    const int q = (b * 2 * g.H + 2 * y + (d >> 1)) * 2 * g.W + 2 * x + (d & 1);
-    const float *s = dout.p + (size_t)q * dout.cs + dout.coff + co;
-    bf16x8 v;
-    for (int j = 0; j < 8; ++j) v[j] = (bf16)s[j];
-    return v;
+  __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
+    if (m >= g.P() || k >= kend) return zero8();
+    const int d = (int)dCout.q((uint32_t)k), co = k - d * Cout;
+    return f32x8_to_bf16(dout.p + (size_t)up_pixel(g, m, d) * dout.cs + dout.coff + co);
   }
-  __device__ __forceinline__ bf16x8 b8(int n, int k) const {
-    if (n >= Cin) return zero8();
+  __device__ __forceinline__ bf16x8 b(int n, int k, int kend, int) const {
+    if (n >= Cin || k >= kend) return zero8();
     return *reinterpret_cast<const bf16x8 *>(WtT + (size_t)n * 4 * Cout + k);
-  }
-  __device__ __forceinline__ void fill_a(bf16 (*S)[LDK], int m0, int k0, int ke, int tid) const {
-    fill_rows<true>(*this, S, m0, k0, ke, tid);
-  }
-  __device__ __forceinline__ void fill_b(bf16 (*S)[LDK], int n0, int k0, int ke, int tid) const {
-    fill_rows<false>(*this, S, n0, k0, ke, tid);
   }
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     if (m >= g.P() || n >= Cin) return;
@@ -319,38 +433,29 @@ struct UpBwdData {
 // db[co] = sum over all output pixels of dOut[., co] (ones column at ci = Cin).
 // M = 4 Cout (m = d*Cout + co), N = Cin + 1, reduction over input pixels, split.
 struct UpBwdWeight {
+  static constexpr int A_LAYOUT = COL, B_LAYOUT = COL;
   Img g;
   View<const float> dout;
   View<const bf16> in;
   int Cin, Cout;
+  Div dCout;
   int chunk;
   float *partial;  // [splits][4*Cout][Cin+1]
   __device__ __forceinline__ void krange(int z, int &b, int &e) const {
     b = z * chunk;
     e = min(g.P(), b + chunk);
   }
-  __device__ __forceinline__ void fill_a(bf16 (*S)[LDK], int m0, int k0, int ke, int tid) const {
-    const int pl = tid >> 3, ml = (tid & 7) * 8;
-    const int p = k0 + pl, m = m0 + ml;
-    bf16x8 v = zero8();
-    if (p < ke && m < 4 * Cout) {
-      const int d = m / Cout, co = m - d * Cout;
-      const int x = p % g.W, t = p / g.W, y = t % g.H, b = t / g.H;
-      const int q = (b * 2 * g.H + 2 * y + (d >> 1)) * 2 * g.W + 2 * x + (d & 1);
-      const float *s = dout.p + (size_t)q * dout.cs + dout.coff + co;
-      for (int j = 0; j < 8; ++j) v[j] = (bf16)s[j];
-    }
-    for (int j = 0; j < 8; ++j) S[ml + j][pl] = v[j];
+  __device__ __forceinline__ bf16x8 a(int m, int p, int kend, int) const {
+    if (p >= kend || m >= 4 * Cout) return zero8();
+    const int d = (int)dCout.q((uint32_t)m), co = m - d * Cout;
+    return f32x8_to_bf16(dout.p + (size_t)up_pixel(g, p, d) * dout.cs + dout.coff + co);
   }
-  __device__ __forceinline__ void fill_b(bf16 (*S)[LDK], int n0, int k0, int ke, int tid) const {
-    const int pl = tid >> 3, nl = (tid & 7) * 8;
-    const int p = k0 + pl, n = n0 + nl;
+  __device__ __forceinline__ bf16x8 b(int n, int p, int kend, int) const {
     bf16x8 v = zero8();
-    if (p < ke) {
-      if (n < Cin) v = *reinterpret_cast<const bf16x8 *>(in.p + (size_t)p * in.cs + in.coff + n);
-      else if (n == Cin) v[0] = (bf16)1.f;
-    }
-    for (int j = 0; j < 8; ++j) S[nl + j][pl] = v[j];
+    if (p >= kend) return v;
+    if (n < Cin) v = *reinterpret_cast<const bf16x8 *>(in.p + (size_t)p * in.cs + in.coff + n);
+    else if (n == Cin) v[0] = (bf16)1.f;
+    return v;
   }
   __device__ __forceinline__ void store(int m, int n, float v, int z) const {
     if (m >= 4 * Cout || n > Cin) return;
@@ -358,24 +463,35 @@ struct UpBwdWeight {
   }
 };
 
-// Sums split partials [splits][M][Kw+1] in fixed order into dW[m][k] (k < Kw)
-// and, for the ones column, db[m mod Cb] (accumulated over the rows sharing it).
+// Sums split partials [splits][M][Kw+1] in a fixed order into dW[m][k] (k < Kw)
+// and, for the ones column, db[c] = sum over rows m = c (mod Cb) of column Kw.
+// A block handles 16 output elements with 16 split groups: group g adds splits
+// g, g+16, g+32, ... in order, then the groups are combined by a fixed tree.
+constexpr int RED_E = 16, RED_G = 16;
 static __global__ __launch_bounds__(256) void k_split_reduce(const float *partial, int splits, int M, int Kw,
-                                                      float *dW, float *db, int Cb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int Nw = Kw + 1;
-  if (i >= M * Kw && i >= Cb) return;
-  if (i < M * Kw) {
-    const int m = i / Kw, k = i - m * Kw;
-    float s = 0.f;
-    for (int z = 0; z < splits; ++z) s += partial[((size_t)z * M + m) * Nw + k];
-    dW[i] = s;
+                                                             float *dW, float *db, int Cb) {
+  __shared__ float sh[RED_G][RED_E + 1];
+  const int el = threadIdx.x % RED_E, gr = threadIdx.x / RED_E;
+  const int e = blockIdx.x * RED_E + el;  // element: dW entries, then biases
+  const int Nw = Kw + 1, nW = M * Kw;
+  float acc = 0.f;
+  if (e < nW) {
+    const int m = e / Kw, k = e - m * Kw;
+    for (int z = gr; z < splits; z += RED_G) acc += partial[((size_t)z * M + m) * Nw + k];
+  } else if (e < nW + Cb) {
+    const int c = e - nW;
+    for (int m = c; m < M; m += Cb)
+      for (int z = gr; z < splits; z += RED_G) acc += partial[((size_t)z * M + m) * Nw + Kw];
   }
-  if (i < Cb) {  // bias of output channel i: rows m with m mod Cb == i
-    float s = 0.f;
-    for (int m = i; m < M; m += Cb)
-      for (int z = 0; z < splits; ++z) s += partial[((size_t)z * M + m) * Nw + Kw];
-    db[i] = s;
+  sh[gr][el] = acc;
+  __syncthreads();
+  for (int w = RED_G / 2; w >= 1; w >>= 1) {
+    if (gr < w) sh[gr][el] += sh[gr + w][el];
+    __syncthreads();
+  }
+  if (gr == 0) {
+    if (e < nW) dW[e] = sh[0][el];
+    else if (e < nW + Cb) db[e - nW] = sh[0][el];
   }
 }
 

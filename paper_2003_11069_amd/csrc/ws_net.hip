@@ -166,20 +166,52 @@ int refresh_weights(ws_net *n) {
   return WS_OK;
 }
 
-template <class Prob>
-void gemm(ws_net *n, const Prob &p, int M, int N, int splits) {
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
-  hipLaunchKernelGGL((k_gemm<Prob>), grid, dim3(256), 0, n->stream, p);
+// Block tile of a GEMM: BN from the output width (32 / 64 / 128), BM = 128
+// unless the tile count would leave the chip idle or the problem needs rows
+// grouped by a divisor (the up-sampling parity).
+struct Tile {
+  int bm, bn;
+};
+
+Tile pick_tile(int M, int N, int row_group) {
+  Tile t{128, N <= 32 ? 32 : (N <= 64 ? 64 : 128)};
+  auto tiles = [&](const Tile &x) { return (int64_t)((M + x.bm - 1) / x.bm) * ((N + x.bn - 1) / x.bn); };
+  if ((row_group && row_group % 128) || tiles(t) < 1024) t.bm = 64;
+  if (t.bn == 128 && tiles(t) < 512) t.bn = 64;
+  return t;
 }
 
-// split count and chunk (pixels per split) for a weight-gradient GEMM
-void split_plan(const ws_net *n, int P, int M, int N, int &splits, int &chunk) {
-  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+// Tile of a split weight-gradient GEMM (small M, wide N; splits fill the chip).
+Tile pick_tile_split(int M, int N) { return Tile{M <= 64 ? 64 : 128, N <= 32 ? 32 : (N <= 64 ? 64 : 128)}; }
+
+template <class Prob, int BMt, int BNt>
+void launch(ws_net *n, const Prob &p, int M, int N, int splits) {
+  dim3 grid((M + BMt - 1) / BMt, (N + BNt - 1) / BNt, splits);
+  hipLaunchKernelGGL((k_gemm<Prob, BMt, BNt>), grid, dim3(256), 0, n->stream, p);
+}
+
+template <class Prob>
+void gemm(ws_net *n, const Prob &p, int M, int N, int splits, Tile t) {
+  if (t.bm == 128) {
+    if (t.bn == 32) launch<Prob, 128, 32>(n, p, M, N, splits);
+    else if (t.bn == 64) launch<Prob, 128, 64>(n, p, M, N, splits);
+    else launch<Prob, 128, 128>(n, p, M, N, splits);
+  } else {
+    if (t.bn == 32) launch<Prob, 64, 32>(n, p, M, N, splits);
+    else if (t.bn == 64) launch<Prob, 64, 64>(n, p, M, N, splits);
+    else launch<Prob, 64, 128>(n, p, M, N, splits);
+  }
+}
+
+// split count and chunk (pixels per split, a multiple of the K step) for a
+// weight-gradient GEMM over P pixels: about 1024 blocks in all
+void split_plan(int P, int M, int N, int &splits, int &chunk) {
+  const Tile t = pick_tile_split(M, N);
+  const int tiles = ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
   int s = std::max(1, 1024 / std::max(tiles, 1));
   s = std::min(s, std::max(1, P / (4 * BK)));
   chunk = ((P + s - 1) / s + BK - 1) / BK * BK;
   splits = (P + chunk - 1) / chunk;
-  (void)n;
 }
 
 template <int KS, bool RELU, bool F32>
@@ -193,7 +225,8 @@ int conv_fwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> 
   p.bias = n->params + c.b_off;
   p.out = out;
   p.outf = outf;
-  gemm(n, p, g.B * g.H * g.W, c.Cout, 1);
+  p.dCin = Div::make(c.Cin);
+  gemm(n, p, g.B * g.H * g.W, c.Cout, 1, pick_tile(g.B * g.H * g.W, c.Cout, 0));
   return WS_OK;
 }
 
@@ -202,27 +235,49 @@ int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> ou
                 : conv_fwd_t<3, false, false>(n, c, g, in, out, View<float>{nullptr, 0, 0});
 }
 
-// weight and bias gradients of a conv layer, then (if din.p) its data gradient
-template <int KS, bool RELU>
-int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act, View<const float> dout,
-               View<float> din, int accumulate) {
-  const int P = g.B * g.H * g.W;
-  const int Kw = KS * KS * c.Cin;
-  int splits, chunk;
-  split_plan(n, P, c.Cout, Kw + 1, splits, chunk);
-  if ((size_t)splits * c.Cout * (Kw + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
-  ConvBwdWeight<KS, RELU> pw;
+// GEMM shape of a conv weight gradient: Cout x (K+1), or transposed when Cout
+// is narrow (the wide im2col dimension then fills the 128-row tiles).
+struct WShape {
+  bool tr;
+  int M, N;
+};
+WShape wshape(int Cout, int Kw1) { return Cout < 64 ? WShape{true, Kw1, Cout} : WShape{false, Cout, Kw1}; }
+
+void launch_split_reduce(ws_net *n, int splits, int M, int Kw, float *dW, float *db, int Cb) {
+  const int64_t elems = (int64_t)M * Kw + Cb;
+  hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((elems + RED_E - 1) / RED_E)), dim3(256), 0, n->stream,
+                     n->scratch, splits, M, Kw, dW, db, Cb);
+}
+
+template <int KS, bool RELU, bool TR>
+void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act,
+                     View<const float> dout, int chunk, int splits, const WShape &ws) {
+  ConvBwdWeight<KS, RELU, TR> pw;
   pw.g = g;
   pw.dout = dout;
   pw.act = act;
   pw.in = in;
   pw.Cin = c.Cin;
   pw.Cout = c.Cout;
+  pw.dCin = Div::make(c.Cin);
   pw.chunk = chunk;
   pw.partial = n->scratch;
-  gemm(n, pw, c.Cout, Kw + 1, splits);
-  hipLaunchKernelGGL(k_split_reduce, dim3(blocks((int64_t)c.Cout * Kw)), dim3(256), 0, n->stream, n->scratch, splits,
-                     c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
+  gemm(n, pw, ws.M, ws.N, splits, pick_tile_split(ws.M, ws.N));
+}
+
+// weight and bias gradients of a conv layer, then (if din.p) its data gradient
+template <int KS, bool RELU>
+int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act, View<const float> dout,
+               View<float> din, int accumulate) {
+  const int P = g.B * g.H * g.W;
+  const int Kw = KS * KS * c.Cin;
+  const WShape ws = wshape(c.Cout, Kw + 1);
+  int splits, chunk;
+  split_plan(P, ws.M, ws.N, splits, chunk);
+  if ((size_t)splits * c.Cout * (Kw + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+  if (ws.tr) conv_bwd_weight<KS, RELU, true>(n, c, g, in, act, dout, chunk, splits, ws);
+  else conv_bwd_weight<KS, RELU, false>(n, c, g, in, act, dout, chunk, splits, ws);
+  launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   if (din.p) {
     ConvBwdData<KS, RELU> pd;
     pd.g = g;
@@ -233,7 +288,8 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     pd.WtT = c.WtT;
     pd.din = din;
     pd.accumulate = accumulate;
-    gemm(n, pd, P, c.Cin, 1);
+    pd.dCout = Div::make(c.Cout);
+    gemm(n, pd, P, c.Cin, 1, pick_tile(P, c.Cin, 0));
   }
   return WS_OK;
 }
@@ -247,14 +303,16 @@ int up_fwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<bf16> out)
   p.Wt = u.Wt;
   p.bias = n->params + u.b_off;
   p.out = out;
-  gemm(n, p, 4 * gin.B * gin.H * gin.W, u.Cout, 1);
+  const int Pin = gin.B * gin.H * gin.W;
+  p.dPin = Div::make(Pin);
+  gemm(n, p, 4 * Pin, u.Cout, 1, pick_tile(4 * Pin, u.Cout, Pin));
   return WS_OK;
 }
 
 int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const float> dout, View<float> din) {
   const int P = gin.B * gin.H * gin.W;
   int splits, chunk;
-  split_plan(n, P, 4 * u.Cout, u.Cin + 1, splits, chunk);
+  split_plan(P, 4 * u.Cout, u.Cin + 1, splits, chunk);
   if ((size_t)splits * 4 * u.Cout * (u.Cin + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
   UpBwdWeight pw;
   pw.g = gin;
@@ -264,9 +322,9 @@ int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const floa
   pw.Cout = u.Cout;
   pw.chunk = chunk;
   pw.partial = n->scratch;
-  gemm(n, pw, 4 * u.Cout, u.Cin + 1, splits);
-  hipLaunchKernelGGL(k_split_reduce, dim3(blocks((int64_t)4 * u.Cout * u.Cin)), dim3(256), 0, n->stream, n->scratch,
-                     splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
+  pw.dCout = Div::make(u.Cout);
+  gemm(n, pw, 4 * u.Cout, u.Cin + 1, splits, pick_tile_split(4 * u.Cout, u.Cin + 1));
+  launch_split_reduce(n, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
   UpBwdData pd;
   pd.g = gin;
   pd.dout = dout;
@@ -274,7 +332,8 @@ int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const floa
   pd.Cout = u.Cout;
   pd.WtT = u.WtT;
   pd.din = din;
-  gemm(n, pd, P, u.Cin, 1);
+  pd.dCout = Div::make(u.Cout);
+  gemm(n, pd, P, u.Cin, 1, pick_tile(P, u.Cin, 0));
   return WS_OK;
 }
 
@@ -289,7 +348,7 @@ int forward(ws_net *n, const float *x, int B) {
   hipLaunchKernelGGL(k_pack_input, dim3(blocks((int64_t)P0 * 8)), dim3(256), 0, n->stream, x, P0, n->cfg.cin,
                      n->xin.p);
   for (int l = 0; l < L; ++l) {
-    Img g{B, imgH(n, l), imgW(n, l)};
+    Img g = Img::make(B, imgH(n, l), imgW(n, l));
     const int C = chans(n, l);
     View<const bf16> in = l == 0 ? cv(n->xin) : cv(n->pool[l]);
     int rc = conv_fwd(n, n->e1[l], g, in, mv(n->mid_e[l]));
@@ -304,7 +363,7 @@ int forward(ws_net *n, const float *x, int B) {
     }
   }
   for (int l = L - 2; l >= 0; --l) {
-    Img gl{B, imgH(n, l), imgW(n, l)}, gu{B, imgH(n, l + 1), imgW(n, l + 1)};
+    Img gl = Img::make(B, imgH(n, l), imgW(n, l)), gu = Img::make(B, imgH(n, l + 1), imgW(n, l + 1));
     View<const bf16> uin = l == L - 2 ? cv(n->bott) : cv(n->dec[l + 1]);
     int rc = up_fwd(n, n->up[l], gu, uin, mv(n->cat[l], 0));
     if (rc) return rc;
@@ -313,7 +372,7 @@ int forward(ws_net *n, const float *x, int B) {
     rc = conv_fwd(n, n->d2[l], gl, cv(n->mid_d[l]), mv(n->dec[l]));
     if (rc) return rc;
   }
-  Img g0{B, n->cfg.H, n->cfg.W};
+  Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
   int rc = conv_fwd_t<1, false, true>(n, n->head, g0, cv(n->dec[0]), View<bf16>{nullptr, 0, 0}, mv(n->y));
   if (rc) return rc;
   HTRY(hipGetLastError());
@@ -322,12 +381,12 @@ int forward(ws_net *n, const float *x, int B) {
 
 int backward(ws_net *n, int B) {
   const int L = n->L;
-  Img g0{B, n->cfg.H, n->cfg.W};
+  Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
   int rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), View<const bf16>{nullptr, 0, 0}, cv(n->dy),
                                 mv(n->ddec[0]), 0);
   if (rc) return rc;
   for (int l = 0; l <= L - 2; ++l) {
-    Img gl{B, imgH(n, l), imgW(n, l)}, gu{B, imgH(n, l + 1), imgW(n, l + 1)};
+    Img gl = Img::make(B, imgH(n, l), imgW(n, l)), gu = Img::make(B, imgH(n, l + 1), imgW(n, l + 1));
     rc = conv_bwd_t<3, true>(n, n->d2[l], gl, cv(n->mid_d[l]), cv(n->dec[l]), cv(n->ddec[l]), mv(n->dmid_d[l]), 0);
     if (rc) return rc;
     rc = conv_bwd_t<3, true>(n, n->d1[l], gl, cv(n->cat[l]), cv(n->mid_d[l]), cv(n->dmid_d[l]), mv(n->dcat[l]), 0);
@@ -338,7 +397,7 @@ int backward(ws_net *n, int B) {
     if (rc) return rc;
   }
   for (int l = L - 1; l >= 0; --l) {
-    Img g{B, imgH(n, l), imgW(n, l)};
+    Img g = Img::make(B, imgH(n, l), imgW(n, l));
     const int C = chans(n, l);
     View<const bf16> eout = l < L - 1 ? cv(n->cat[l], C) : cv(n->bott);
     View<const float> deout = l < L - 1 ? cv(n->dcat[l], C) : cv(n->dbott);
@@ -349,7 +408,7 @@ int backward(ws_net *n, int B) {
     rc = conv_bwd_t<3, true>(n, n->e1[l], g, in, cv(n->mid_e[l]), cv(n->dmid_e[l]), din, 0);
     if (rc) return rc;
     if (l > 0) {  // route the pooled gradient into the level l-1 encoder output
-      Img gp{B, imgH(n, l - 1), imgW(n, l - 1)};
+      Img gp = Img::make(B, imgH(n, l - 1), imgW(n, l - 1));
       const int Cp = chans(n, l - 1);
       const int64_t cnt = (int64_t)B * g.H * g.W * Cp;
       hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, gp, cv(n->cat[l - 1], Cp), Cp,
@@ -458,17 +517,27 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   if (!rc) rc = buf(n, n->dy, 0, 8);
   // split-K scratch: at most 1024/tiles splits of a weight-gradient matrix
   size_t worst = 0;
-  auto need = [&](int M, int N) {
-    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-    const int s = std::max(1, 1024 / std::max(tiles, 1));
-    worst = std::max(worst, (size_t)(s + 1) * M * N);
-  };
-  for (auto &x : n->e1) need(x.Cout, 9 * x.Cin + 1);
-  for (auto &x : n->e2) need(x.Cout, 9 * x.Cin + 1);
-  for (auto &x : n->d1) need(x.Cout, 9 * x.Cin + 1);
-  for (auto &x : n->d2) need(x.Cout, 9 * x.Cin + 1);
-  for (auto &x : n->up) need(4 * x.Cout, x.Cin + 1);
-  need(8, n->C0 + 1);
+  for (int B = 1; B <= c->max_batch; ++B) {  // splits depend on the batch
+    auto need = [&](int l, int M, int N) {
+      int splits, chunk;
+      split_plan(B * imgH(n, l) * imgW(n, l), M, N, splits, chunk);
+      worst = std::max(worst, (size_t)splits * M * N);
+    };
+    auto conv = [&](int lv, const Conv &cv) {
+      const WShape w = wshape(cv.Cout, cv.KS * cv.KS * cv.Cin + 1);
+      need(lv, w.M, w.N);
+    };
+    for (int l = 0; l < L; ++l) {
+      conv(l, n->e1[l]);
+      conv(l, n->e2[l]);
+      if (l < L - 1) {
+        conv(l, n->d1[l]);
+        conv(l, n->d2[l]);
+        need(l + 1, 4 * n->up[l].Cout, n->up[l].Cin + 1);  // over the input (coarser) pixels
+      }
+    }
+    conv(0, n->head);
+  }
   n->scratch_floats = worst;
   if (!rc) rc = dalloc(n, &n->scratch, worst);
   n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W * 8);

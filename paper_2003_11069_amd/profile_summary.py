@@ -68,9 +68,11 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--kernel", required=True, help="substring of the kernel name")
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--copy-bytes", type=int, required=True, help="bytes read (and written) per copy dispatch")
+    ap.add_argument("--fetch", default=None)
+    ap.add_argument("--write", default=None)
+    ap.add_argument("--copy-bytes", type=int, default=None, help="bytes read (and written) per copy dispatch")
+    ap.add_argument("--top", type=int, default=12, help="kernels listed from the trace")
+    ap.add_argument("--no-hash", action="store_true", help="omit the LB source hash (other kernels)")
     ap.add_argument("--alg-bytes", type=float, default=None, help="algorithmic bytes per launch")
     ap.add_argument("--command", required=True, help="the command that produced the runs")
     ap.add_argument("--workload", default="")
@@ -78,38 +80,40 @@ def main(argv=None):
     a = ap.parse_args(argv)
 
     stats = trace_stats(a.trace)
-    fetch = counter_per_dispatch(a.fetch, "FETCH_SIZE")
-    write = counter_per_dispatch(a.write, "WRITE_SIZE")
-    kf, kw = _match(fetch, a.kernel), _match(write, a.kernel)
-    cf, cw = _match(fetch, "k_copy_probe"), _match(write, "k_copy_probe")
-    # the first copy dispatch only initialises its source (write only)
-    copy_fetch_kib = statistics.median(fetch[cf][1:])
-    copy_write_kib = statistics.median(write[cw][1:])
-    s_f = a.copy_bytes / (copy_fetch_kib * 1024.0)
-    s_w = a.copy_bytes / (copy_write_kib * 1024.0)
-    f_kib = statistics.mean(fetch[kf])
-    w_kib = statistics.mean(write[kw])
-    hbm = f_kib * 1024.0 * s_f + w_kib * 1024.0 * s_w
     lines = [f"# rocprofv3 summary: {a.kernel} {a.workload}".rstrip(),
-             f"command: {a.command}",
-             f"kernel_source_sha256: {kernel_source_hash()}",
-             "",
-             "## kernel trace (--kernel-trace --stats)",
-             f"{'kernel':<70} {'calls':>6} {'avg_us':>10} {'total_us':>12} {'pct':>6}"]
-    for n, k, t, av, p in stats[:12]:
-        lines.append(f"{n[:70]:<70} {k:>6} {av:>10.3f} {t:>12.1f} {p:>6.2f}")
+             f"command: {a.command}"]
+    if not a.no_hash:
+        lines.append(f"kernel_source_sha256: {kernel_source_hash()}")
     lines += ["",
-              "## HBM counters (--pmc FETCH_SIZE, --pmc WRITE_SIZE; KiB per dispatch)",
-              f"copy kernel ({a.copy_bytes} B read + written per dispatch): "
-              f"FETCH_SIZE {copy_fetch_kib:.1f} KiB, WRITE_SIZE {copy_write_kib:.1f} KiB",
-              f"scale factors: fetch {s_f:.4f}, write {s_w:.4f}",
-              f"{a.kernel}: FETCH_SIZE {f_kib:.1f} KiB x {s_f:.4f} = {f_kib * 1024 * s_f:.0f} B, "
-              f"WRITE_SIZE {w_kib:.1f} KiB x {s_w:.4f} = {w_kib * 1024 * s_w:.0f} B "
-              f"({len(fetch[kf])} / {len(write[kw])} dispatches)",
-              f"hbm_bytes_per_launch: {hbm:.0f}"]
-    if a.alg_bytes:
-        lines.append(f"algorithmic_bytes_per_launch: {a.alg_bytes:.0f} (measured / algorithmic = "
-                     f"{hbm / a.alg_bytes:.3f})")
+              "## kernel trace (--kernel-trace --stats)",
+              f"{'kernel':<70} {'calls':>6} {'avg_us':>10} {'total_us':>12} {'pct':>6}"]
+    for n, k, t, av, p in stats[:a.top]:
+        lines.append(f"{n[:70]:<70} {k:>6} {av:>10.3f} {t:>12.1f} {p:>6.2f}")
+    if a.fetch and a.write and a.copy_bytes:
+        fetch = counter_per_dispatch(a.fetch, "FETCH_SIZE")
+        write = counter_per_dispatch(a.write, "WRITE_SIZE")
+        kf, kw = _match(fetch, a.kernel), _match(write, a.kernel)
+        cf, cw = _match(fetch, "k_copy_probe"), _match(write, "k_copy_probe")
+        # the first copy dispatch only initialises its source (write only)
+        copy_fetch_kib = statistics.median(fetch[cf][1:])
+        copy_write_kib = statistics.median(write[cw][1:])
+        s_f = a.copy_bytes / (copy_fetch_kib * 1024.0)
+        s_w = a.copy_bytes / (copy_write_kib * 1024.0)
+        f_kib = statistics.mean(fetch[kf])
+        w_kib = statistics.mean(write[kw])
+        hbm = f_kib * 1024.0 * s_f + w_kib * 1024.0 * s_w
+        lines += ["",
+                  "## HBM counters (--pmc FETCH_SIZE, --pmc WRITE_SIZE; KiB per dispatch)",
+                  f"copy kernel ({a.copy_bytes} B read + written per dispatch): "
+                  f"FETCH_SIZE {copy_fetch_kib:.1f} KiB, WRITE_SIZE {copy_write_kib:.1f} KiB",
+                  f"scale factors: fetch {s_f:.4f}, write {s_w:.4f}",
+                  f"{a.kernel}: FETCH_SIZE {f_kib:.1f} KiB x {s_f:.4f} = {f_kib * 1024 * s_f:.0f} B, "
+                  f"WRITE_SIZE {w_kib:.1f} KiB x {s_w:.4f} = {w_kib * 1024 * s_w:.0f} B "
+                  f"({len(fetch[kf])} / {len(write[kw])} dispatches)",
+                  f"hbm_bytes_per_launch: {hbm:.0f}"]
+        if a.alg_bytes:
+            lines.append(f"algorithmic_bytes_per_launch: {a.alg_bytes:.0f} (measured / algorithmic = "
+                         f"{hbm / a.alg_bytes:.3f})")
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
