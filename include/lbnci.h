@@ -122,6 +122,10 @@ int lb_set_populations(lb_handle *h, const double *f1, const double *f2);
 /* Advance n >= 0 steps (collide, then pull-stream).  Asynchronous.
  * Errors: LB_ESTATE before initialisation, LB_EDEVICE on launch failure. */
 int lb_step(lb_handle *h, int64_t n);
+/* 1 while lb_step replays windows of 16 plain steps (no observable recording
+ * inside, profiling off) from a captured hipGraph, 0 after a capture failed
+ * (plain launches from then on; the results are identical either way). */
+int lb_graphs(const lb_handle *h);
 
 /* Observables of the current state (synchronises the stream).
  * Returns LB_ENUMERIC if a NaN/Inf was seen (out is still filled). */

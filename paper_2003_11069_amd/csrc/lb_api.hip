@@ -281,6 +281,9 @@ void lb_destroy(lb_handle *h) {
   (void)hipFree(h->partials);
   (void)hipFree(h->obs);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k)
+    if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
 
@@ -339,12 +342,54 @@ int lb_set_populations(lb_handle *h, const double *f1, const double *f2) {
   return upload_explicit(h, xt, xc);
 }
 
+// Plain steps replayed from a graph: GRAPH_STEPS (even) kernel pairs captured
+// once per starting copy on a private stream, launched on the handle's stream.
+static constexpr int GRAPH_STEPS = 16;
+
+static int graph_steps(lb_handle *h) {
+  const int c0 = h->cur;
+  if (!h->graph[c0]) {
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = h->stream;
+    h->stream = h->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    int rc = LB_OK;
+    for (int k = 0; k < GRAPH_STEPS && e == hipSuccess && rc == LB_OK; ++k) rc = dispatch(h, STEP);
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    h->stream = user;
+    h->cur = c0;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && rc == LB_OK) e = hipGraphInstantiate(&h->graph[c0], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess || rc != LB_OK) {
+      (void)hipGetLastError();
+      h->graph[c0] = nullptr;
+      return fail(LB_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+  }
+  HIP_TRY(hipGraphLaunch(h->graph[c0], h->stream));
+  return LB_OK;
+}
+
 int lb_step(lb_handle *h, int64_t n) {
   if (!h) return fail(LB_EINVAL, "NULL handle");
   if (n < 0) return fail(LB_EINVAL, "negative step count");
   if (!h->initialised) return fail(LB_ESTATE, "lb_step before initialisation");
-  for (int64_t k = 0; k < n; ++k) {
-    const bool rec = h->p.obs_every > 0 && (h->t % h->p.obs_every) == 0;
+  const int64_t oe = h->p.obs_every;
+  for (int64_t k = 0; k < n;) {
+    // a window of plain steps (no recording step inside) goes through a graph
+    const bool plain_window =
+        oe <= 0 || (h->t % oe != 0 && (h->t / oe) == ((h->t + GRAPH_STEPS - 1) / oe));
+    if (h->graphs_ok && !h->profile && !h->explicit_src && n - k >= GRAPH_STEPS && plain_window) {
+      if (graph_steps(h) == LB_OK) {
+        h->t += GRAPH_STEPS;
+        k += GRAPH_STEPS;
+        continue;
+      }
+      h->graphs_ok = 0;  // fall back to plain launches from now on
+    }
+    const bool rec = oe > 0 && (h->t % oe) == 0;
     int rc = dispatch(h, rec ? STEP_OBS : STEP);
     if (rc) return rc;
     if (rec) {
@@ -352,9 +397,12 @@ int lb_step(lb_handle *h, int64_t n) {
       if (rc) return rc;
     }
     h->t += 1;
+    k += 1;
   }
   return LB_OK;
 }
+
+int lb_graphs(const lb_handle *h) { return h ? h->graphs_ok : -1; }
 
 int lb_observables(lb_handle *h, lb_obs *out) {
   if (!h || !out) return fail(LB_EINVAL, "NULL argument");

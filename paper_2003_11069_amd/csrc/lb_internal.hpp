@@ -75,6 +75,10 @@ struct lb_handle {
   int64_t t = 0;
   int xcd_remap = LBNCI_XCD_REMAP;
   int64_t bytes = 0;
+  // replay of GRAPH_STEPS plain steps from a hipGraph, one per starting copy
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graphs_ok = 1;
   // per-kernel event timing
   int profile = 0;
   std::vector<hipEvent_t> ev;  // triples: before phase, between, after main

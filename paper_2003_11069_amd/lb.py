@@ -63,6 +63,7 @@ def load_library(path: str = LIB_PATH):
         "lb_init_fields": ([vp, dp, dp, dp], C.c_int),
         "lb_set_populations": ([vp, dp, dp], C.c_int),
         "lb_step": ([vp, C.c_int64], C.c_int),
+        "lb_graphs": ([vp], C.c_int),
         "lb_observables": ([vp, P(lb_obs)], C.c_int),
         "lb_get_fields": ([vp, dp, dp, dp], C.c_int),
         "lb_get_populations": ([vp, dp, dp], C.c_int),
@@ -258,6 +259,11 @@ class Lattice:
         f1 = np.zeros((self.Q, self.N)); f2 = np.zeros((self.Q, self.N))
         _check(self.lib.lb_get_populations(self.h, _dp(f1), _dp(f2)))
         return f1, f2
+
+    @property
+    def graphs(self) -> bool:
+        """True while plain steps are replayed from captured hipGraphs."""
+        return self.lib.lb_graphs(self.h) == 1
 
     def profile(self, enable: bool = True):
         _check(self.lib.lb_profile(self.h, int(enable)))

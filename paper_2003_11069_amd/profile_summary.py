@@ -26,14 +26,16 @@ import statistics
 _PKG = os.path.dirname(os.path.abspath(__file__))
 
 
+KERNEL_SOURCES = ("lb_kernels.hpp", "lb_internal.hpp")  # kernels and their launch shapes
+
+
 def kernel_source_hash() -> str:
-    """Hash of the lattice Boltzmann kernel sources (csrc/lb_*.hpp, lb_*.hip)."""
+    """Hash of the lattice Boltzmann kernel code and launch configuration."""
     h = hashlib.sha256()
     csrc = os.path.join(_PKG, "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hpp", ".hip")) and f.startswith("lb_"):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
