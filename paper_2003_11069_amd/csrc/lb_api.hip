@@ -3,6 +3,7 @@
 #include "lb_internal.hpp"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -54,21 +55,28 @@ int blocks_phase(const lb_handle *h) {
 }
 
 
+// Kernel launches; with events (profiling) the start/stop events travel in the
+// kernel's own dispatch packet, so they time the kernel alone.
+template <class K, class A>
+void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0, hipEvent_t e1, const A &a) {
+  if (e0) hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, a);
+  else hipLaunchKernelGGL(kernel, grid, block, 0, st, a);
+}
+
 template <int D, typename S, typename R, int SRC, int MODE>
-void launch_main(lb_handle *h, const Args<S, R> &a) {
+void launch_main(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int nb = blocks_main(h);
   if constexpr (D == 2)
-    hipLaunchKernelGGL((k_main<D, S, R, SRC, MODE, BY2, TZ2, H2>), dim3(nb), dim3(64, BY2), 0,
-                       h->stream, a);
+    launch(k_main<D, S, R, SRC, MODE, BY2, TZ2, H2>, dim3(nb), dim3(64, BY2), h->stream, e0, e1, a);
   else
-    hipLaunchKernelGGL((k_main<D, S, R, SRC, MODE, BY3, TZ3, H3, LBNCI_WPE_MAIN3>), dim3(nb),
-                       dim3(64, BY3), 0, h->stream, a);
+    launch(k_main<D, S, R, SRC, MODE, BY3, TZ3, H3, LBNCI_WPE_MAIN3>, dim3(nb), dim3(64, BY3), h->stream,
+           e0, e1, a);
 }
 
 template <int D, typename S, typename R, int SRC>
-void launch_phase(lb_handle *h, const Args<S, R> &a) {
-  hipLaunchKernelGGL((k_phase<D, S, R, SRC, (D == 3 ? TZP3 : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1)>),
-                     dim3(blocks_phase(h)), dim3(64, 4), 0, h->stream, a);
+void launch_phase(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  launch(k_phase<D, S, R, SRC, (D == 3 ? TZP3 : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1)>, dim3(blocks_phase(h)),
+         dim3(64, 4), h->stream, e0, e1, a);
 }
 
 // One pass over the lattice in the given mode; STEP modes write the other copy.
@@ -78,28 +86,24 @@ int run_pass(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t
   Args<S, R> a = make_args<S, R>(h, in, out);
   a.f_out0 = o0; a.f_out1 = o1; a.f_out2 = o2; a.i_out = io;
   const bool timed = h->profile && (mode == STEP || mode == STEP_OBS);
-  hipEvent_t e[3];
-  if (timed) {
-    for (int k = 0; k < 3; ++k) HIP_TRY(hipEventCreate(&e[k]));
-    HIP_TRY(hipEventRecord(e[0], h->stream));
-  }
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (timed)
+    for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&e[k]));
   if (h->explicit_src) {
-    launch_phase<D, S, R, EXPLICIT>(h, a);
-    if (timed) HIP_TRY(hipEventRecord(e[1], h->stream));
+    launch_phase<D, S, R, EXPLICIT>(h, a, e[0], e[1]);
     switch (mode) {
-      case STEP: launch_main<D, S, R, EXPLICIT, STEP>(h, a); break;
-      case STEP_OBS: launch_main<D, S, R, EXPLICIT, STEP_OBS>(h, a); break;
+      case STEP: launch_main<D, S, R, EXPLICIT, STEP>(h, a, e[2], e[3]); break;
+      case STEP_OBS: launch_main<D, S, R, EXPLICIT, STEP_OBS>(h, a, e[2], e[3]); break;
       case OBSERVE: launch_main<D, S, R, EXPLICIT, OBSERVE>(h, a); break;
       case FIELDS: launch_main<D, S, R, EXPLICIT, FIELDS>(h, a); break;
       case POPS: launch_main<D, S, R, EXPLICIT, POPS>(h, a); break;
       default: launch_main<D, S, R, EXPLICIT, DIAG>(h, a); break;
     }
   } else {
-    launch_phase<D, S, R, PULL>(h, a);
-    if (timed) HIP_TRY(hipEventRecord(e[1], h->stream));
+    launch_phase<D, S, R, PULL>(h, a, e[0], e[1]);
     switch (mode) {
-      case STEP: launch_main<D, S, R, PULL, STEP>(h, a); break;
-      case STEP_OBS: launch_main<D, S, R, PULL, STEP_OBS>(h, a); break;
+      case STEP: launch_main<D, S, R, PULL, STEP>(h, a, e[2], e[3]); break;
+      case STEP_OBS: launch_main<D, S, R, PULL, STEP_OBS>(h, a, e[2], e[3]); break;
       case OBSERVE: launch_main<D, S, R, PULL, OBSERVE>(h, a); break;
       case FIELDS: launch_main<D, S, R, PULL, FIELDS>(h, a); break;
       case POPS: launch_main<D, S, R, PULL, POPS>(h, a); break;
@@ -107,10 +111,8 @@ int run_pass(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t
     }
   }
   HIP_TRY(hipGetLastError());
-  if (timed) {
-    HIP_TRY(hipEventRecord(e[2], h->stream));
-    for (int k = 0; k < 3; ++k) h->ev.push_back(e[k]);
-  }
+  if (timed)
+    for (int k = 0; k < 4; ++k) h->ev.push_back(e[k]);
   if (mode == STEP || mode == STEP_OBS) {
     h->cur = out;
     h->explicit_src = 0;
@@ -514,10 +516,10 @@ int lb_kernel_times(lb_handle *h, double *ms_phase, double *ms_main, int64_t *la
   HIP_TRY(hipStreamSynchronize(h->stream));
   double a = 0, b = 0;
   int64_t n = 0;
-  for (size_t k = 0; k + 2 < h->ev.size(); k += 3) {
+  for (size_t k = 0; k + 3 < h->ev.size(); k += 4) {
     float t0 = 0, t1 = 0;
     HIP_TRY(hipEventElapsedTime(&t0, h->ev[k], h->ev[k + 1]));
-    HIP_TRY(hipEventElapsedTime(&t1, h->ev[k + 1], h->ev[k + 2]));
+    HIP_TRY(hipEventElapsedTime(&t1, h->ev[k + 2], h->ev[k + 3]));
     a += t0;
     b += t1;
     ++n;

@@ -81,7 +81,7 @@ struct lb_handle {
   int graphs_ok = 1;
   // per-kernel event timing
   int profile = 0;
-  std::vector<hipEvent_t> ev;  // triples: before phase, between, after main
+  std::vector<hipEvent_t> ev;  // quadruples: phase start/stop, main start/stop
   // lattice tables (host)
   int c[27][3];
   double w[27];

@@ -26,16 +26,17 @@ import statistics
 _PKG = os.path.dirname(os.path.abspath(__file__))
 
 
-KERNEL_SOURCES = ("lb_kernels.hpp", "lb_internal.hpp")  # kernels and their launch shapes
-
-
 def kernel_source_hash() -> str:
-    """Hash of the lattice Boltzmann kernel code and launch configuration."""
+    """Hash of the lattice Boltzmann kernel code (csrc/lb_kernels.hpp) and of
+    the launch-shape definitions (the #define lines of csrc/lb_internal.hpp)."""
     h = hashlib.sha256()
     csrc = os.path.join(_PKG, "csrc")
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "lb_kernels.hpp"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "lb_internal.hpp"), "rb") as fh:
+        for line in fh:
+            if line.lstrip().startswith(b"#define LBNCI_") or line.lstrip().startswith(b"#define LB_"):
+                h.update(line)
     return h.hexdigest()[:16]
 
 
