@@ -37,7 +37,7 @@ class _Params(C.Structure):
     _fields_ = [("lattice", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("walls_y", C.c_int32), ("tau", C.c_double), ("A_s", C.c_double),
                 ("beta", C.c_double), ("A_nci", C.c_double), ("h_min", C.c_double),
-                ("h_max", C.c_double), ("force", C.c_double * 3)]
+                ("h_max", C.c_double), ("force", C.c_double * 3), ("tau2", C.c_double)]
 
 
 def _load():
@@ -97,11 +97,12 @@ class Params:
     h_min: float = 2.0
     h_max: float = 4.0
     force: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    tau2: float = 0.0
 
     def to_c(self) -> _Params:
         p = _Params()
         for k in ("lattice", "nx", "ny", "nz", "walls_y", "tau", "A_s", "beta", "A_nci",
-                  "h_min", "h_max"):
+                  "h_min", "h_max", "tau2"):
             setattr(p, k, getattr(self, k))
         for a in range(3):
             p.force[a] = float(self.force[a])

@@ -101,6 +101,10 @@ static void collide(const lbo_params *p, int Q, int32_t (*c)[3], const double *w
     double fi = f1[i] + f2[i];
     for (int a = 0; a < 3; ++a) j[a] += c[i][a] * fi;
   }
+  /* relaxation rate: one mixture tau, or the phase-weighted harmonic mean of
+     the two components' relaxation times (viscosity-ratio variant) */
+  double omega = 1.0 / p->tau;
+  if (p->tau2 > 0) omega = (rho1 / rho) / p->tau + (rho2 / rho) / p->tau2;
   double u[3], uF[3];
   for (int a = 0; a < 3; ++a) {
     u[a] = j[a] / rho;
@@ -117,7 +121,7 @@ static void collide(const lbo_params *p, int Q, int32_t (*c)[3], const double *w
     double cG = c[i][0] * Gh[0] + c[i][1] * Gh[1] + c[i][2] * Gh[2];
     /* Omega1 (BGK) + forcing (EDM) + Omega2 (perturbation) */
     double pert = 0.5 * p->A_s * g * (w[i] * cG * cG - w[i] / 3.0);
-    double fp = fi - (fi - feq) / p->tau + (feqF - feq) + pert;
+    double fp = fi - (fi - feq) * omega + (feqF - feq) + pert;
     /* Omega3: recolouring with cos(phi_i) = c_i.G / (|c_i||G|) */
     double cnorm = sqrt((double)(c[i][0] * c[i][0] + c[i][1] * c[i][1] + c[i][2] * c[i][2]));
     double cosphi = (cnorm > 0) ? cG / cnorm : 0.0;

@@ -45,6 +45,9 @@ typedef struct {
   double beta;              /* recolouring parameter                          */
   double A_nci, h_min, h_max; /* NCI strength and range                       */
   double force[3];          /* uniform body-force density (= -grad p)         */
+  double tau2;              /* relaxation time of component 2; 0: both use tau.
+                               Otherwise tau is component 1's and the node's
+                               1/tau_mix = (rho1/rho)/tau + (rho2/rho)/tau2  */
 } lbo_params;
 
 typedef struct lbo lbo;

@@ -314,3 +314,16 @@ def unet_batch_exact(B: int, H: int, W: int, cin: int, cout: int, seed: int = 0)
     x = rng.integers(-64, 64, (B, H, W, cin)) / 16.0
     t = rng.integers(-64, 64, (B, H, W, cout)) / 16.0
     return x.astype(np.float32), t.astype(np.float32)
+
+
+def two_layer_channel(nx=4, ny=34, y_i=16.5, tau1=1.0, tau2=2.0, force=1e-6, **kw) -> Case:
+    """Wall-bounded D2Q9 channel with component 1 below the flat interface
+    y = y_i and component 2 above it (tanh profile, width 2), each with its
+    own relaxation time; uniform body force along x."""
+    y = np.arange(ny, dtype=np.float64)
+    psi = np.tanh((y_i - y) / 2.0)
+    r1 = np.tile(((1 + psi) / 2)[:, None], (1, nx)).ravel()
+    r2 = np.tile(((1 - psi) / 2)[:, None], (1, nx)).ravel()
+    p = base_params(lattice=0, nx=nx, ny=ny, nz=1, walls_y=1, tau=tau1, tau2=tau2, A_nci=0.0,
+                    force=(force, 0.0, 0.0), **kw)
+    return Case(p, r1, r2)

@@ -173,3 +173,53 @@ def test_nci_prevents_coalescence():
         r1, r2, _ = o.fields()
         n[A] = _n_droplets(((r1 - r2) / (r1 + r2)).reshape(ny, nx))
     assert n[0.0] == 1 and n[0.02] == 2
+
+
+def _viscous_profile(nu_rho, F):
+    """Finite-volume solution of d/dy(rho nu du/dy) = -F on the fluid rows of a
+    channel with half-way walls (harmonic face averages), given rho*nu per row."""
+    n = len(nu_rho)
+    A = np.zeros((n, n))
+    for k in range(n):
+        for j in (k - 1, k + 1):
+            if 0 <= j < n:
+                face = 2 * nu_rho[k] * nu_rho[j] / (nu_rho[k] + nu_rho[j])
+                A[k, j] += face
+                A[k, k] -= face
+            else:  # wall half a spacing away
+                A[k, k] -= 2 * nu_rho[k]
+    return np.linalg.solve(A, -F * np.ones(n))
+
+
+def test_two_layer_channel_flow():
+    """Viscosity-ratio variant: two stratified fluids (nu2 = 3 nu1) driven by a
+    body force reach the velocity profile of the viscous momentum balance
+    d/dy(nu(y) du/dy) = -F, with nu(y) from the phase-weighted relaxation
+    time of each row, and the flux of the sharp two-layer solution."""
+    tau1, tau2, F = 1.0, 2.0, 1e-6
+    case = synth.two_layer_channel(tau1=tau1, tau2=tau2, force=F)
+    p = case.params
+    o = oracle.Oracle(oracle.Params(**p))
+    o.init_fields(case.rho1, case.rho2)
+    o.step(20000)
+    r1, r2, u = o.fields()
+    ny, nx = p["ny"], p["nx"]
+    r1 = r1.reshape(ny, nx)[1:-1, 0]
+    r2 = r2.reshape(ny, nx)[1:-1, 0]
+    ux = u[0].reshape(ny, nx)[1:-1, 0]
+    rho = r1 + r2
+    tau = 1.0 / ((r1 / rho) / tau1 + (r2 / rho) / tau2)
+    ufd = _viscous_profile(rho * (tau - 0.5) / 3.0, F)
+    err = np.abs(ux - ufd).max() / ufd.max()
+    # sharp interface at eta_i between walls at eta = 0 and H
+    H, eta_i = ny - 2, 16.0
+    n1, n2 = (tau1 - 0.5) / 3, (tau2 - 0.5) / 3
+    M = np.array([[eta_i, -(eta_i - H)], [n1, -n2]])
+    A1, A2 = np.linalg.solve(M, [-F / (2 * n2) * (eta_i ** 2 - H ** 2) + F / (2 * n1) * eta_i ** 2, 0.0])
+    eta = np.arange(H) + 0.5
+    ush = np.where(eta < eta_i, -F / (2 * n1) * eta ** 2 + A1 * eta,
+                   -F / (2 * n2) * (eta ** 2 - H ** 2) + A2 * (eta - H))
+    assert err <= 0.03, err
+    assert ux.sum() == pytest.approx(ush.sum(), rel=0.02)
+    # a single viscosity (tau1 everywhere) would carry 1.8 times this flux
+    assert ux.sum() < 0.6 * F * H ** 3 / (12 * n1)

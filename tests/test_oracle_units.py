@@ -172,6 +172,36 @@ def test_bgk_relaxation(lat):
     assert np.abs(o2).max() == 0.0  # single component stays single
 
 
+@pytest.mark.parametrize("lat", [oracle.D2Q9, oracle.D3Q27])
+def test_two_tau_relaxation(lat):
+    """Viscosity-ratio variant: with component relaxation times tau1, tau2 a
+    node relaxes at the phase-weighted harmonic rate
+    1/tau = (rho1/rho)/tau1 + (rho2/rho)/tau2 (mass fractions), and
+    tau2 = tau1 is the single-tau collision."""
+    c, w, _ = oracle.lattice(lat)
+    d = _dim(lat)
+    rng = np.random.default_rng(6)
+    tau1, tau2 = 0.73, 1.9
+    f1 = 0.3 * w * (1 + rng.uniform(-0.1, 0.1, len(w)))
+    f2 = 0.7 * w * (1 + rng.uniform(-0.1, 0.1, len(w)))
+    p = _params(lat, A_s=0.0, beta=0.0, tau=tau1, tau2=tau2)
+    o1, o2 = oracle.collide_node(p, f1, f2, np.zeros(3), np.zeros(3))
+    cc = c[:, :d].astype(float)
+    f = f1 + f2
+    rho = f.sum()
+    u = f @ cc / rho
+    E = oracle.equilibrium(lat, rho, u)
+    Pi = lambda g: np.einsum("i,ia,ib->ab", g, cc, cc)
+    omega = (f1.sum() / rho) / tau1 + (f2.sum() / rho) / tau2
+    np.testing.assert_allclose(Pi(o1 + o2) - Pi(E), (1 - omega) * (Pi(f) - Pi(E)), atol=1e-16)
+    assert abs(o1.sum() - f1.sum()) < 1e-15 and abs(o2.sum() - f2.sum()) < 1e-15
+    p_same = _params(lat, A_s=0.0, beta=0.0, tau=tau1, tau2=tau1)
+    p_one = _params(lat, A_s=0.0, beta=0.0, tau=tau1)
+    for a, b in zip(oracle.collide_node(p_same, f1, f2, np.zeros(3), np.zeros(3)),
+                    oracle.collide_node(p_one, f1, f2, np.zeros(3), np.zeros(3))):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-16)
+
+
 def test_A_h_table():
     """A_h[h] against the hand-tabulated golden values (h_min=2, h_max=4)."""
     tab = np.loadtxt(os.path.join(GOLDEN, "A_h_table.txt"))
