@@ -81,6 +81,11 @@ typedef struct {
   int32_t conv_window; /* convergence window W in recorded samples (0 = off)  */
   int32_t conv_m;      /* consecutive windows required                         */
   double conv_eps;     /* relative change of the windowed flow rate           */
+  double tau2;         /* viscosity-ratio variant: relaxation time of
+                          component 2 (> 1/2), tau then being component 1's;
+                          a node relaxes at 1/tau_mix = (rho1/rho)/tau +
+                          (rho2/rho)/tau2.  0 = one mixture tau (the paper's
+                          model)                                              */
 } lb_params;
 
 /* Observables of the current state, accumulated in FP64 in a fixed order:

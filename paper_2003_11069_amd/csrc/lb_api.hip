@@ -154,6 +154,7 @@ int validate(const lb_params *p) {
   if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 29)
     return fail(LB_EINVAL, "lattice too large (at most 2^29 nodes)");
   if (!(p->tau > 0.5)) return fail(LB_EINVAL, "tau must exceed 1/2");
+  if (!(p->tau2 == 0.0 || p->tau2 > 0.5)) return fail(LB_EINVAL, "tau2 must be 0 or exceed 1/2");
   if (!(p->beta >= 0.0 && p->beta <= 1.0)) return fail(LB_EINVAL, "beta must lie in [0,1]");
   if (!(p->A_s >= 0.0)) return fail(LB_EINVAL, "A_s must be >= 0");
   if (!(p->A_nci >= 0.0)) return fail(LB_EINVAL, "A_nci must be >= 0");

@@ -102,6 +102,8 @@ inline lbk::Args<S, R> make_args(lb_handle *h, int in, int out) {
   a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.walls = p.walls_y;
   a.N = (uint32_t)h->N;
   a.tau_inv = (R)(1.0 / p.tau);
+  a.two_tau = p.tau2 > 0 ? 1 : 0;
+  a.tau2_inv = (R)(p.tau2 > 0 ? 1.0 / p.tau2 : 1.0 / p.tau);
   a.half_As = (R)(0.5 * p.A_s);
   a.beta = (R)p.beta;
   a.A = (R)p.A_nci;

@@ -106,6 +106,8 @@ struct Args {
   int nx, ny, nz, walls;
   uint32_t N;
   R tau_inv, half_As, beta, A, h_min, h_max;
+  R tau2_inv;         // component 2 (two_tau): 1/tau_mix = (rho1/rho)/tau + (rho2/rho)/tau2
+  int two_tau;
   R F[3];
   int smax;           // floor(h_max)
   State<S, R> in, out;
@@ -576,7 +578,10 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       // this removes the FP32 update's and the storage's rounding of it).  a
       // is taken against the density of the stored populations so that the
       // component-1 mass is carried exactly.
-      const float om = tinv, omc = 1.f - om, om1 = om - 1.f;
+      // relaxation rate: one mixture tau, or the phase-weighted harmonic mean
+      // of the two components' relaxation times (viscosity-ratio variant)
+      const float om = A.two_tau ? (float)(r1 * irho * (A.tau_inv - A.tau2_inv) + A.tau2_inv) : tinv;
+      const float omc = 1.f - om, om1 = om - 1.f;
       const float cdr = om * drf - pg * (1.0f / 3.0f);
       const uint32_t nb = n * (uint32_t)sizeof(S), NB = A.N * (uint32_t)sizeof(S);
       R sum_q = 0;

@@ -170,6 +170,37 @@ def test_graph_replay_bit_identical(name):
     assert o1["Q_window"] == o2["Q_window"] and o1["Q"] == o2["Q"]
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_two_tau_parity(storage):
+    """Viscosity-ratio variant (tau2): a two-layer channel and a droplet
+    channel against the oracle after 200 steps (FP32 at the 1e-5 bar; FP16
+    within its stated budget), and the tau2 = tau run equal to tau2 = 0."""
+    say(f"[gpu] two relaxation times, {storage}")
+    tol_r, tol_u = (1e-5, 1e-5) if storage == "fp32" else (2e-3, 0.2)
+    for case in (synth.two_layer_channel(tau1=1.0, tau2=2.0, force=1e-5),
+                 synth.channel_2d(synth.channel_spec(104, Lx=64, Ly=50), jitter=0.5)):
+        params = dict(case.params)
+        params.setdefault("tau2", 0.0)
+        if params["tau2"] == 0.0:
+            params["tau2"] = 0.6 if params["tau"] > 1.0 else 1.7
+        c2 = synth.Case(params, case.rho1, case.rho2, case.u)
+        o, g = make_pair(c2, storage=storage)
+        o.step(200)
+        g.step(200)
+        e = field_errors(o, g, fluid_mask(params, c2.N))
+        say(f"  {params['nx']}x{params['ny']} tau {params['tau']:.3f} tau2 {params['tau2']:.3f}: {e}")
+        assert e["rho1"] <= tol_r and e["rho2"] <= tol_r and e["u"] <= tol_u
+    case = synth.two_droplets_2d(nx=64, ny=40, R=8, gap=3.0, jitter=0.4, seed=3)
+    p = P.Params.from_dict(case.params)
+    g1 = P.Lattice(p)
+    g2 = P.Lattice(P.Params.from_dict(case.params, tau2=p.tau))
+    for g in (g1, g2):
+        g.init_fields(case.rho1, case.rho2)
+        g.step(50)
+    for x, y in zip(g1.fields(), g2.fields()):
+        np.testing.assert_allclose(x, y, rtol=0, atol=1e-12)
+
+
 def test_resync_parity_config2_full_size():
     """Full-size 3-D droplet channel (256x64x64, D3Q27, walls, NCI, body
     force): the GPU is loaded with the oracle's populations and both take one
