@@ -1,0 +1,118 @@
+"""Pins of the droplet-analysis oracle (CPU only): components against a
+brute-force flood fill, periodic merging on hand-built masks, and the
+discrete closed form of central-difference vorticity."""
+import math
+from collections import deque
+
+import numpy as np
+import pytest
+
+from oracle import analysis as A
+
+
+def _flood(mask, periodic):
+    """Independent brute force: BFS with explicit neighbour wrapping."""
+    nz, ny, nx = mask.shape
+    lab = -np.ones(mask.shape, np.int64)
+    dims = (nz, ny, nx)
+    for start in range(mask.size):
+        z, y, x = np.unravel_index(start, mask.shape)
+        if not mask[z, y, x] or lab[z, y, x] >= 0:
+            continue
+        lab[z, y, x] = start
+        q = deque([(z, y, x)])
+        while q:
+            c = q.popleft()
+            for ax in range(3):
+                for s in (-1, 1):
+                    n = list(c)
+                    n[ax] += s
+                    if n[ax] < 0 or n[ax] >= dims[ax]:
+                        if not periodic[ax] or dims[ax] < 2:
+                            continue
+                        n[ax] %= dims[ax]
+                    n = tuple(n)
+                    if mask[n] and lab[n] < 0:
+                        lab[n] = start
+                        q.append(n)
+    return lab
+
+
+@pytest.mark.parametrize("shape,periodic,seed", [((1, 9, 12), (True, True, True), 0),
+                                                 ((1, 9, 12), (True, False, True), 1),
+                                                 ((4, 5, 6), (True, True, True), 2),
+                                                 ((4, 6, 5), (True, False, True), 3)])
+def test_components_match_flood_fill(shape, periodic, seed):
+    rng = np.random.default_rng(seed)
+    for _ in range(20):
+        mask = rng.uniform(size=shape) < 0.45
+        lab, n = A.components(mask, periodic)
+        ref = _flood(mask, periodic)
+        assert np.array_equal(lab, ref)
+        assert n == len(np.unique(ref[ref >= 0]))
+
+
+def test_periodic_merge_and_walls():
+    m = np.zeros((1, 6, 10), bool)
+    m[0, 2:4, 0:2] = True   # touches x = 0 ...
+    m[0, 2:4, 8:10] = True  # ... and x = nx-1: one droplet through the boundary
+    m[0, 0, 5] = m[0, 5, 5] = True  # rows 0 and ny-1: adjacent only if y is periodic
+    lab, n = A.components(m, (True, True, True))
+    assert n == 2 and lab[0, 2, 9] == lab[0, 2, 0] == 20 and lab[0, 5, 5] == lab[0, 0, 5] == 5
+    lab, n = A.components(m, (True, False, True))
+    assert n == 3
+    assert A.droplet_sizes(lab) == {5: 1, 20: 8, 55: 1}
+
+
+def test_vorticity_discrete_closed_form():
+    nx, ny = 16, 12
+    kx, ky = 2 * math.pi / nx, 2 * math.pi * 2 / ny
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    u = np.stack([np.sin(ky * y), np.sin(kx * x)]).reshape(2, -1)
+    w = A.vorticity(u, nx, ny, 1, walls_y=0)
+    ref = np.cos(kx * x) * math.sin(kx) - np.cos(ky * y) * math.sin(ky)
+    np.testing.assert_allclose(w, ref.ravel(), atol=1e-14)
+    # 3-D: u_x = sin(k z) gives omega_y = cos(k z) sin(k) only
+    nz = 8
+    k = 2 * math.pi / nz
+    z = np.arange(nz)[:, None, None] * np.ones((1, 4, 5))
+    u3 = np.zeros((3, nz * 4 * 5))
+    u3[0] = np.sin(k * z).ravel()
+    w3 = A.vorticity(u3, 5, 4, nz, walls_y=0)
+    np.testing.assert_allclose(w3[1], (np.cos(k * z) * math.sin(k)).ravel(), atol=1e-14)
+    assert np.abs(w3[0]).max() == 0 and np.abs(w3[2]).max() == 0
+
+
+def test_vorticity_linear_shear_and_solid_rotation():
+    # linear fields: the central difference is exact away from the wrap, so
+    # shear u_x = a y gives omega_z = -a and solid rotation u = W x r gives 2 W
+    nx, ny, nz = 7, 9, 8
+    a = 0.3
+    y = np.arange(ny)[None, :, None] * np.ones((nz, 1, nx))
+    u = np.zeros((2, ny * nx))
+    u[0] = (a * y[0]).ravel()
+    w = A.vorticity(u, nx, ny, 1, walls_y=1).reshape(ny, nx)
+    assert np.all(w[0] == 0) and np.all(w[-1] == 0)
+    np.testing.assert_allclose(w[2:-2], -a, rtol=1e-14)
+    # next to a wall the wall's u = 0 enters: (u(y+1) - 0) / 2
+    np.testing.assert_allclose(w[1], -a * 2 / 2, rtol=1e-14)
+    np.testing.assert_allclose(w[-2], -(0 - a * (ny - 3)) / 2, rtol=1e-14)
+    Om = np.array([0.11, -0.07, 0.05])
+    z, yy, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.stack([x - 3.0, yy - 4.0, z - 3.5])
+    U = np.cross(Om[:, None, None, None], r, axis=0)
+    w3 = A.vorticity(U.reshape(3, -1), nx, ny, nz, walls_y=0).reshape(3, nz, ny, nx)
+    inner = w3[:, 1:-1, 1:-1, 1:-1]
+    np.testing.assert_allclose(inner, np.broadcast_to(2 * Om[:, None, None, None], inner.shape),
+                               rtol=1e-13)
+
+
+def test_dispersed_mask():
+    nx, ny = 4, 5
+    r1 = np.array([0.6, 0.4, 0.5, 0.0] * 5)
+    r2 = np.array([0.4, 0.6, 0.5, 0.0] * 5)
+    m = A.dispersed_mask(r1, r2, nx, ny, 1, walls_y=1)
+    assert m.shape == (1, ny, nx)
+    assert not m[0, 0].any() and not m[0, -1].any()
+    assert np.array_equal(m[0, 1:-1], np.tile([True, False, False, False], (3, 1)))
+    assert A.dispersed_mask(r1, r2, nx, ny, 1, walls_y=0)[0, 0, 0]
