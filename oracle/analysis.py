@@ -13,6 +13,16 @@ definitions used here:
   by the wall rows in y (or periodic in y without walls);
 * canonical label of a node: the smallest node index n = x + nx (y + ny z)
   in its droplet; -1 outside the dispersed phase;
+* droplet table, in ascending order of canonical label: volume V_d (node
+  count) and centroid.  Each node contributes its offset from the droplet's
+  root node, taken in the periodic directions as the image in
+  [-floor(L/2), L - 1 - floor(L/2)]; the centroid is root + (sum of
+  offsets)/V, moved back into [0, L) (meaningful for droplets shorter than
+  half the period);
+* rows (hex-n, named by the number of droplet rows across the channel,
+  Results): droplets of at least a quarter of the mean volume, sorted by
+  centroid y; a gap in y larger than half the equivalent diameter of the
+  median droplet starts a new row;
 * vorticity: omega = curl u by central differences over the node grid
   (periodic wrap in the periodic directions; wall rows hold u = 0).
 
@@ -22,6 +32,8 @@ exact central difference of linear shear and of solid rotation, and by the
 discrete closed form for sinusoidal velocity fields.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 import scipy.ndimage as ndi
@@ -91,6 +103,47 @@ def droplet_sizes(labels):
     lab = lab[lab >= 0]
     roots, counts = np.unique(lab, return_counts=True)
     return dict(zip(roots.tolist(), counts.tolist()))
+
+
+def droplet_table(labels, nx, ny, nz, walls_y):
+    """(roots, volumes, centroids [count, 3] as (x, y, z)) of a label array
+    [nz, ny, nx], in ascending root order."""
+    lab = np.asarray(labels).reshape(nz, ny, nx)
+    roots = np.unique(lab[lab >= 0])
+    vols = np.zeros(len(roots), np.int64)
+    cen = np.zeros((len(roots), 3))
+    z, y, x = np.nonzero(lab >= 0)
+    r = lab[z, y, x]
+    order = np.searchsorted(roots, r)
+    coord = (x, y, z)
+    L = (nx, ny, nz)
+    per = (True, not walls_y, True)
+    rc = (roots % nx, (roots // nx) % ny, roots // (nx * ny))
+    np.add.at(vols, order, 1)
+    for d in range(3):
+        off = coord[d] - rc[d][order]
+        if per[d]:
+            h = L[d] // 2
+            off = np.mod(off + h, L[d]) - h
+        s = np.zeros(len(roots), np.int64)
+        np.add.at(s, order, off)
+        c = rc[d].astype(np.float64) + s.astype(np.float64) / vols.astype(np.float64)
+        if per[d]:
+            c = np.where(c < 0, c + L[d], np.where(c >= L[d], c - L[d], c))
+        cen[:, d] = c
+    return roots, vols, cen
+
+
+def rows(centroid_y, volumes, dim):
+    """Number of droplet rows across the channel (hex-n)."""
+    v = np.asarray(volumes, np.float64)
+    if len(v) == 0:
+        return 0
+    keep = v >= 0.25 * v.mean()
+    y = np.sort(np.asarray(centroid_y, np.float64)[keep])
+    vm = float(np.median(v[keep]))
+    d_eq = 2.0 * (math.sqrt(vm / math.pi) if dim == 2 else (3.0 * vm / (4.0 * math.pi)) ** (1.0 / 3.0))
+    return 1 + int(np.count_nonzero(np.diff(y) > 0.5 * d_eq))
 
 
 def vorticity(u, nx, ny, nz, walls_y):

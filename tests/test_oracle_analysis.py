@@ -116,3 +116,72 @@ def test_dispersed_mask():
     assert not m[0, 0].any() and not m[0, -1].any()
     assert np.array_equal(m[0, 1:-1], np.tile([True, False, False, False], (3, 1)))
     assert A.dispersed_mask(r1, r2, nx, ny, 1, walls_y=0)[0, 0, 0]
+
+
+def _disks(shape, centres, R):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    m = np.zeros(shape, bool)
+    for cx, cy, cz in centres:
+        dx = (x - cx + nx / 2) % nx - nx / 2
+        dz = (z - cz + nz / 2) % nz - nz / 2 if nz > 1 else 0
+        m |= dx * dx + (y - cy) ** 2 + dz * dz <= R * R
+    return m
+
+
+def test_droplet_table_centroids_through_the_boundaries():
+    nx, ny, nz = 20, 16, 16
+    # a sphere centred on the x and z periodic faces, and one in the bulk
+    # (both shorter than half of each period)
+    m = _disks((nz, ny, nx), [(0.0, 7.0, 0.0), (10.0, 8.0, 6.0)], 3.2)
+    lab, n = A.components(m, (True, False, True))
+    roots, vols, cen = A.droplet_table(lab, nx, ny, nz, walls_y=1)
+    assert n == 2 and vols.sum() == m.sum() and list(roots) == sorted(roots)
+    # brute force: shift the lattice so that the droplet does not wrap, take
+    # the plain mean, shift back; lattice spheres about a node are symmetric,
+    # so the centroid is the centre itself
+    for r, v, c, (sx, sz), ctr in zip(roots, vols, cen, [(10, 8), (0, 0)],
+                                      [(0.0, 7.0, 0.0), (10.0, 8.0, 6.0)]):
+        sh = np.roll(np.roll(lab, sx, axis=2), sz, axis=0)
+        z, y, x = np.nonzero(sh == r)
+        assert len(x) == v
+        ref = ((x.mean() - sx) % nx, y.mean(), (z.mean() - sz) % nz)
+        np.testing.assert_allclose(c, ref, atol=1e-12)
+        np.testing.assert_allclose(c, ctr, atol=1e-12)
+
+
+@pytest.mark.parametrize("n_rows", [1, 2, 3])
+def test_rows_of_hexagonal_packings(n_rows):
+    R, nx = 6.0, 120
+    a = 2 * R + 3  # gap of 3 nodes between neighbours
+    pitch = a * math.sqrt(3) / 2
+    ny = int(2 * R + 4 + (n_rows - 1) * pitch + 2)
+    cs = []
+    for r in range(n_rows):
+        for i in range(int(nx / a)):
+            cs.append(((i + 0.5 * (r % 2)) * nx / int(nx / a), R + 2.5 + r * pitch, 0.0))
+    m = _disks((1, ny, nx), cs, R)
+    m[:, 0] = m[:, -1] = False
+    lab, n = A.components(m, (True, False, True))
+    assert n == len(cs)
+    roots, vols, cen = A.droplet_table(lab, nx, ny, 1, walls_y=1)
+    assert A.rows(cen[:, 1], vols, 2) == n_rows
+    # debris below a quarter of the mean volume does not make a row
+    m[0, ny // 2 + 1 if n_rows == 1 else 1, 3] = True
+    lab, n2 = A.components(m, (True, False, True))
+    roots, vols, cen = A.droplet_table(lab, nx, ny, 1, walls_y=1)
+    assert A.rows(cen[:, 1], vols, 2) == n_rows
+
+
+@pytest.mark.parametrize("seed,n_rows", [(0, 5), (2, 3), (3, 3), (4, 5)])
+def test_rows_of_synthetic_channels(seed, n_rows):
+    """Channels whose droplets do not touch: the count and the number of rows
+    are those the generator placed."""
+    import synth
+    c = synth.channel_2d(synth.channel_spec(seed))
+    p = c.params
+    m = A.dispersed_mask(c.rho1, c.rho2, p["nx"], p["ny"], 1, 1)
+    lab, n = A.components(m, (True, False, True))
+    assert n == c.info["n_droplets"]
+    roots, vols, cen = A.droplet_table(lab, p["nx"], p["ny"], 1, 1)
+    assert A.rows(cen[:, 1], vols, 2) == n_rows
