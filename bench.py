@@ -87,7 +87,7 @@ def main(argv=None):
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp32_f32"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep", "unet"])
+    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep", "unet", "analysis"])
     ap.add_argument("--batch", type=int, default=16, help="U-Net training batch (--workload unet)")
     ap.add_argument("--mode", default="persistent", choices=["persistent", "launch"])
     a = ap.parse_args(argv)
@@ -105,6 +105,8 @@ def main(argv=None):
         return bench_sweep(a)
     if a.workload == "unet":
         return bench_unet(a)
+    if a.workload == "analysis":
+        return bench_analysis(a)
     case = synth.hex_channel_3d()
     prm = case.params
     dim = 3
@@ -229,6 +231,48 @@ def bench_unet(a):
                       "batch": B, "params": net.n_params, "gflop_per_sample_fwd": round(fwd / B / 1e9, 3)},
            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
                         "frac": round(tflops / 2500.0, 4), "traffic": None}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_analysis(a):
+    """Droplet analysis and vorticity of the 3-D benchmark channel after
+    --warmup steps: min(--steps, 50) calls of each, device time per call from
+    events on the library's stream (FIELDS pass plus analysis kernels), and
+    the host-inclusive time per call (copies of labels and tables included)."""
+    import synth
+    import paper_2003_11069_amd as P
+    case = synth.hex_channel_3d()
+    prm = case.params
+    L = P.Lattice(P.Params.from_dict(prm, storage=P.STORAGE[a.storage]))
+    L.init_fields(case.rho1, case.rho2, case.u)
+    L.step(a.warmup)
+    L.droplets()
+    L.vorticity()
+    n = max(1, min(a.steps, 50))
+    dev_d = dev_w = 0.0
+    t0 = time.perf_counter()
+    for _ in range(n):
+        d = L.droplets()
+        dev_d += L.analysis_times()["ms_droplets"]
+    t1 = time.perf_counter()
+    for _ in range(n):
+        L.vorticity()
+        dev_w += L.analysis_times()["ms_vorticity"]
+    t2 = time.perf_counter()
+    N = L.N
+    ms_d, ms_w = dev_d / n, dev_w / n
+    out = {"metric": "droplet analysis throughput", "value": round(N / (ms_d * 1e-3) / 1e6, 1),
+           "unit": "Mnodes/s", "n_gpus": 1, "steps": n, "warmup": a.warmup,
+           "ms_per_step": round(ms_d, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic (seeded droplet packing)",
+           "config": {"workload": "D3Q27 droplet channel 256x64x64 after the warm-up steps",
+                      "nodes": N, "storage": a.storage},
+           "droplets": {"count": d["count"], "dispersed": d["dispersed"], "rows": d["rows"],
+                        "device_ms": round(ms_d, 4),
+                        "host_ms": round((t1 - t0) / n * 1e3, 3)},
+           "vorticity": {"device_ms": round(ms_w, 4), "host_ms": round((t2 - t1) / n * 1e3, 3),
+                         "Mnodes_per_s": round(N / (ms_w * 1e-3) / 1e6, 1)}}
     print(json.dumps(out), flush=True)
     return 0
 

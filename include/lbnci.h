@@ -174,6 +174,55 @@ int lb_kernel_times(lb_handle *h, double *ms_phase, double *ms_main, int64_t *la
  * Allocates and frees two device buffers. */
 int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double *gbps);
 
+/* ---- Droplet-level analysis (Results: droplet count and volume, the
+ * hex-n arrangements named by their number of droplet rows, vorticity of the
+ * flow) ----------------------------------------------------------------
+ * Droplets are the connected components of the dispersed phase: the fluid
+ * nodes with psi = (rho1 - rho2)/(rho1 + rho2) > 0 in the current fields (the
+ * rho1, rho2 of lb_get_fields, psi evaluated in FP64), under face adjacency
+ * (4 neighbours in 2-D, 6 in 3-D), periodic in x and z, and in y when
+ * walls_y == 0.  The label of a droplet is the smallest node index
+ * n = x + nx*(y + ny*z) in it.  Both calls run one lattice pass in FIELDS mode
+ * into a device arena that the handle allocates on first use (about 120 bytes
+ * per node) and keeps until lb_destroy.  Lattices of 2^31 nodes or more are
+ * rejected (LB_EINVAL).  LB_ESTATE before initialisation, LB_ENOMEM when the
+ * arena cannot be allocated, LB_EDEVICE on a HIP failure. */
+typedef struct {
+  int64_t count;     /* number of droplets */
+  int64_t dispersed; /* number of nodes with psi > 0 */
+  int32_t rows;      /* droplet rows across the channel (hex-n): droplets of at least a
+                        quarter of the mean volume, sorted by centroid y; a gap in y above
+                        half the equivalent diameter (disk in 2-D, sphere in 3-D) of their
+                        median volume starts a new row; 0 without droplets */
+} lb_droplet_stats;
+
+/* Labels the droplets of the current state and lists them in ascending label
+ * order.  All outputs are host arrays owned by the caller; any may be NULL.
+ *   label    N int32: each node's droplet label, -1 outside the dispersed phase;
+ *   root     cap int64: the label of each listed droplet;
+ *   volume   cap int64: its node count V_d;
+ *   centroid 3*cap doubles, (x, y, z) per droplet: the root's coordinates plus
+ *            the mean offset of the droplet's nodes from the root, each offset
+ *            taken along periodic axes as the image in
+ *            [-floor(L/2), L-1-floor(L/2)], the result moved back into [0, L)
+ *            (meaningful for droplets shorter than half of each period).
+ * Only the first min(count, cap) droplets are listed; stats->count is the
+ * full count.  cap < 0 is LB_EINVAL.  Synchronises the stream. */
+int lb_droplets(lb_handle *h, lb_droplet_stats *stats, int32_t *label, int64_t cap, int64_t *root,
+                int64_t *volume, double *centroid);
+
+/* Vorticity omega = curl u of the current velocity (the u of lb_get_fields)
+ * by central differences between nearest nodes, (u(x+e) - u(x-e))/2 per
+ * axis, wrapping along periodic axes; wall rows hold u = 0 and receive
+ * omega = 0.  omega: host, N doubles for D2Q9 (omega_z), 3*N for D3Q27
+ * (omega_x, omega_y, omega_z blocks).  Synchronises the stream. */
+int lb_vorticity(lb_handle *h, double *omega);
+
+/* Device time (ms) of the last lb_droplets and lb_vorticity calls: the FIELDS
+ * pass plus the analysis kernels, between events on the handle's stream
+ * (0 if the call has not been made).  Either pointer may be NULL. */
+int lb_analysis_times(const lb_handle *h, double *ms_droplets, double *ms_vorticity);
+
 /* ---- Batched stepping of many independent lattices ("channels") --------
  * For sweeps of the kind the paper runs over pressure gradient and NCI
  * strength (Results: flow rate versus driving), many small lattices of

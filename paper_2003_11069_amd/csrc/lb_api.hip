@@ -283,6 +283,7 @@ void lb_destroy(lb_handle *h) {
   (void)hipFree(h->xc);
   (void)hipFree(h->partials);
   (void)hipFree(h->obs);
+  analysis_free(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   for (int k = 0; k < 2; ++k)
     if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);

@@ -79,6 +79,11 @@ struct lb_handle {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int graphs_ok = 1;
+  // droplet analysis and vorticity: one device arena, allocated on first use
+  void *ana = nullptr;
+  size_t ana_bytes = 0;
+  hipEvent_t ana_ev[2] = {nullptr, nullptr};
+  double ana_ms[2] = {0.0, 0.0};  // last lb_droplets, lb_vorticity device time
   // per-kernel event timing
   int profile = 0;
   std::vector<hipEvent_t> ev;  // quadruples: phase start/stop, main start/stop
@@ -93,6 +98,8 @@ namespace lbi {
 int dispatch(lb_handle *h, int mode, double *o0 = nullptr, double *o1 = nullptr,
              double *o2 = nullptr, int32_t *io = nullptr);
 int validate(const lb_params *p);
+// Releases the droplet-analysis arena and events of a handle.
+void analysis_free(lb_handle *h);
 int reduce_obs(lb_handle *h, int record);
 // Kernel arguments of a handle reading state copy `in` and writing `out`.
 template <typename S, typename R>

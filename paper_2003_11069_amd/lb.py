@@ -45,6 +45,10 @@ class lb_obs(C.Structure):
                 ("Q_window", C.c_double), ("converged", C.c_int32), ("flags", C.c_int32)]
 
 
+class lb_droplet_stats(C.Structure):
+    _fields_ = [("count", C.c_int64), ("dispersed", C.c_int64), ("rows", C.c_int32)]
+
+
 _lib = None
 
 
@@ -76,6 +80,10 @@ def load_library(path: str = LIB_PATH):
         "lb_profile": ([vp, C.c_int], C.c_int),
         "lb_kernel_times": ([vp, dp, dp, P(C.c_int64)], C.c_int),
         "lb_copy_probe": ([C.c_int64, C.c_int, vp, dp, dp], C.c_int),
+        "lb_droplets": ([vp, P(lb_droplet_stats), ip, C.c_int64, P(C.c_int64), P(C.c_int64), dp],
+                        C.c_int),
+        "lb_vorticity": ([vp, dp], C.c_int),
+        "lb_analysis_times": ([vp, dp, dp], C.c_int),
         "lb_batch_create": ([P(lb_params), C.c_int32, vp, P(vp)], C.c_int),
         "lb_batch_init_fields": ([vp, C.c_int32, dp, dp, dp], C.c_int),
         "lb_batch_step": ([vp, C.c_int64, C.c_int32], C.c_int),
@@ -273,6 +281,31 @@ class Lattice:
         a = C.c_double(); b = C.c_double(); n = C.c_int64()
         _check(self.lib.lb_kernel_times(self.h, C.byref(a), C.byref(b), C.byref(n)))
         return {"ms_phase": a.value, "ms_main": b.value, "launches": n.value}
+
+    def droplets(self, labels: bool = True, cap: int | None = None) -> dict:
+        """Droplets of the current state (lb_droplets): count, dispersed node
+        count, rows (hex-n), per-node labels and the table in label order."""
+        cap = self.N // 2 + 1 if cap is None else cap
+        st = lb_droplet_stats()
+        lab = np.empty(self.N, np.int32) if labels else None
+        root = np.empty(cap, np.int64); vol = np.empty(cap, np.int64); cen = np.empty((cap, 3))
+        i64 = C.POINTER(C.c_int64)
+        _check(self.lib.lb_droplets(self.h, C.byref(st), _ip(lab), cap, root.ctypes.data_as(i64),
+                                    vol.ctypes.data_as(i64), _dp(cen)))
+        k = min(st.count, cap)
+        return {"count": st.count, "dispersed": st.dispersed, "rows": st.rows, "labels": lab,
+                "roots": root[:k].copy(), "volumes": vol[:k].copy(), "centroids": cen[:k].copy()}
+
+    def vorticity(self):
+        """curl u of the current state (lb_vorticity): [N] in 2-D, [3, N] in 3-D."""
+        w = np.empty((1 if self.p.dim == 2 else 3) * self.N)
+        _check(self.lib.lb_vorticity(self.h, _dp(w)))
+        return w if self.p.dim == 2 else w.reshape(3, self.N)
+
+    def analysis_times(self):
+        a = C.c_double(); b = C.c_double()
+        _check(self.lib.lb_analysis_times(self.h, C.byref(a), C.byref(b)))
+        return {"ms_droplets": a.value, "ms_vorticity": b.value}
 
     def nci(self):
         psi = np.zeros(self.N); fr = np.zeros(self.p.dim * self.N); hit = np.zeros(self.N, np.int32)
