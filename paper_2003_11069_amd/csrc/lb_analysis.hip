@@ -6,13 +6,15 @@
 // Droplets.  The dispersed phase is the set of fluid nodes with
 // psi = (rho1 - rho2)/(rho1 + rho2) > 0, evaluated in FP64 from the fields
 // that the lattice pass in FIELDS mode writes.  Components under face
-// adjacency are found with a lock-free union-find over a parent array in HBM:
-// every parent points to a smaller node index of the same component, links
-// are made with atomicMin on a root, so the root of each final tree is the
-// smallest node index of its component -- the canonical label, independent of
-// the order in which the wavefronts run.  Volumes and centroid offsets are
-// integer sums (exact, order-independent); droplets are listed in ascending
-// label order through a block count / scan / write sequence.
+// adjacency are found by union-find in two passes: inside 64-wide tiles in
+// LDS (x-runs from wavefront ballots, then the remaining tile edges), then
+// across tile faces on a parent array in HBM.  Every parent points to a
+// smaller node index of the same component and links are made with atomicMin
+// on a root, so the root of each final tree is the smallest node index of its
+// component -- the canonical label, independent of the order in which the
+// wavefronts run.  Volumes and centroid offsets are integer sums (exact,
+// order-independent); droplets are listed in ascending label order through a
+// block count / scan / write sequence.
 //
 // Vorticity: central differences of the FP64 velocity between nearest nodes.
 #include "lb_internal.hpp"
@@ -47,14 +49,20 @@ __device__ __forceinline__ bool wall_row(const Geo &g, int y) {
   return g.walls && (y == 0 || y == g.ny - 1);
 }
 
-// Tile of the local labelling pass: 64 x TY x TZ nodes, 1024 per block of
-// TPB threads (four nodes per thread).
+// Tile of the local labelling pass: 64 x TY x TZ nodes per block of TPB
+// threads (a whole number of nodes per thread).
+#ifndef LBA_TY3
+#define LBA_TY3 4
+#endif
+#ifndef LBA_TZ3
+#define LBA_TZ3 4
+#endif
 template <int D>
 struct Tile {
-  static constexpr int TX = 64, TY = (D == 2) ? 16 : 4, TZ = (D == 2) ? 1 : 4;
+  static constexpr int TX = 64, TY = (D == 2) ? 16 : LBA_TY3, TZ = (D == 2) ? 1 : LBA_TZ3;
   static constexpr int NODES = TX * TY * TZ;
+  static_assert(NODES % TPB == 0, "whole nodes per thread");
 };
-static_assert(Tile<2>::NODES == CHUNK && Tile<3>::NODES == CHUNK, "one tile per CHUNK");
 
 template <int D>
 __host__ __device__ __forceinline__ int tiles_x(const Geo &g) { return (g.nx + Tile<D>::TX - 1) / Tile<D>::TX; }
@@ -117,12 +125,13 @@ __device__ __forceinline__ void tile_origin(const Geo &g, int &x0, int &y0, int 
 // union-find in LDS, then parent[n] = global index of the node's local root
 // (-1 outside the dispersed phase).  Local and global node order agree, so a
 // local root is also the smallest global index of its local component.  The
-// per-root sums of the stats pass are cleared here.
+// four result counters are cleared here.
 template <int D>
 __global__ __launch_bounds__(TPB) void k_cc_local(const double *__restrict__ r1,
                                                   const double *__restrict__ r2, int32_t *parent,
-                                                  uint32_t *vol, unsigned long long *sums, Geo g) {
+                                                  unsigned long long *counters, Geo g) {
   using T = Tile<D>;
+  if (blockIdx.x == 0 && threadIdx.x < 4) counters[threadIdx.x] = 0ull;
   __shared__ int32_t lp[T::NODES];
   int x0, y0, z0;
   tile_origin<D>(g, x0, y0, z0);
@@ -138,21 +147,28 @@ __global__ __launch_bounds__(TPB) void k_cc_local(const double *__restrict__ r1,
         const double psi = rho > 0.0 ? (a - b) / rho : -1.0;
         m = psi > 0.0;
       }
-      vol[n] = 0u;
-      sums[n] = 0ull;
-      sums[(size_t)g.N + n] = 0ull;
-      sums[2 * (size_t)g.N + n] = 0ull;
     }
-    lp[li] = m ? li : -1;
+    // one tile row is one wavefront (lane = x offset): a dispersed node points
+    // at the first node of its run along x, which joins the run without atomics
+    const uint64_t M = __ballot(m);
+    const int xl = li % T::TX;
+    const uint64_t gaps = ~M & ((1ull << xl) - 1ull);
+    const int start = gaps ? 64 - __clzll(gaps) : 0;
+    lp[li] = m ? li - xl + start : -1;
   }
   __syncthreads();
+  // +y and +z edges inside the tile; of a run of such edges along x whose end
+  // nodes are joined by their x-runs, only the first is needed
   for (int k = 0; k < PER; ++k) {
     const int li = threadIdx.x + TPB * k;
     if (lp[li] < 0) continue;
     const int xl = li % T::TX, yl = (li / T::TX) % T::TY, zl = li / (T::TX * T::TY);
-    if (xl + 1 < T::TX && lp[li + 1] >= 0) unite<true>(lp, li, li + 1);
-    if (yl + 1 < T::TY && lp[li + T::TX] >= 0) unite<true>(lp, li, li + T::TX);
-    if (D == 3 && zl + 1 < T::TZ && lp[li + T::TX * T::TY] >= 0) unite<true>(lp, li, li + T::TX * T::TY);
+    const bool left = xl > 0 && lp[li - 1] >= 0;
+    if (yl + 1 < T::TY && lp[li + T::TX] >= 0 && !(left && lp[li - 1 + T::TX] >= 0))
+      unite<true>(lp, li, li + T::TX);
+    constexpr int PZ = T::TX * T::TY;
+    if (D == 3 && zl + 1 < T::TZ && lp[li + PZ] >= 0 && !(left && lp[li - 1 + PZ] >= 0))
+      unite<true>(lp, li, li + PZ);
   }
   __syncthreads();
   for (int k = 0; k < PER; ++k) {
@@ -213,11 +229,20 @@ __global__ __launch_bounds__(TPB) void k_cc_border(int32_t *parent, Geo g) {
 }
 
 // parent[n] = root of n (the canonical label); the trees are final here.
-__global__ __launch_bounds__(TPB) void k_cc_flatten(int32_t *parent, Geo g) {
+// Roots clear their slots of the per-root sums of the stats pass.
+__global__ __launch_bounds__(TPB) void k_cc_flatten(int32_t *parent, uint32_t *vol,
+                                                    unsigned long long *sums, Geo g) {
   const int32_t n = blockIdx.x * TPB + threadIdx.x;
   if (n >= g.N) return;
   int32_t p = parent[n];
-  if (p < 0 || p == n) return;
+  if (p < 0) return;
+  if (p == n) {
+    vol[n] = 0u;
+    sums[n] = 0ull;
+    sums[(size_t)g.N + n] = 0ull;
+    sums[2 * (size_t)g.N + n] = 0ull;
+    return;
+  }
   int32_t q = parent[p];
   while (q != p) {
     p = q;
@@ -248,23 +273,26 @@ __device__ __forceinline__ long long wave_sum(long long v) {
 // Per-root volume and coordinate-offset sums, and the dispersed-node count.
 // Each wavefront walks STATS_ITER consecutive 64-node chunks; within a chunk
 // the lanes are grouped by root, each group summed across the wave, and the
-// sums carried while the root stays the same, so one droplet costs one set of
-// atomics per wavefront rather than per node.
-constexpr int STATS_ITER = 8;
-__global__ __launch_bounds__(TPB) void k_cc_stats(const int32_t *__restrict__ label, uint32_t *vol,
-                                                  unsigned long long *sums, Geo g,
-                                                  unsigned long long *dispersed) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+// sums carried while the root stays the same.  A change of root flushes the
+// carry with atomics; the final carries of the block's wavefronts (in node
+// order) are merged where they share a root before their atomics, so a
+// droplet costs one set of atomics per block it spans rather than per node.
+constexpr int STATS_ITER = 4, STATS_TPB = 1024, STATS_WAVES = STATS_TPB / 64;
+__global__ __launch_bounds__(STATS_TPB) void k_cc_stats(const int32_t *__restrict__ label, uint32_t *vol,
+                                                        unsigned long long *sums, Geo g,
+                                                        unsigned long long *dispersed) {
+  __shared__ int32_t s_root[STATS_WAVES];
+  __shared__ long long s_acc[STATS_WAVES][4];
+  __shared__ long long s_total[STATS_WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t wave = (int64_t)blockIdx.x * STATS_WAVES + wv;
   int32_t cur = -1;
   long long acc[4] = {0, 0, 0, 0};
   long long total = 0;
-  auto flush = [&]() {
-    if (cur >= 0 && lane == 0) {
-      atomicAdd(vol + cur, (uint32_t)acc[0]);
-      for (int d = 0; d < 3; ++d)
-        if (acc[d + 1]) atomicAdd(sums + (size_t)d * g.N + cur, (unsigned long long)acc[d + 1]);
-    }
+  auto flush = [&](int32_t r, const long long *v) {
+    atomicAdd(vol + r, (uint32_t)v[0]);
+    for (int d = 0; d < 3; ++d)
+      if (v[d + 1]) atomicAdd(sums + (size_t)d * g.N + r, (unsigned long long)v[d + 1]);
   };
   for (int it = 0; it < STATS_ITER; ++it) {
     const int64_t n = (wave * STATS_ITER + it) * 64 + lane;
@@ -287,20 +315,41 @@ __global__ __launch_bounds__(TPB) void k_cc_stats(const int32_t *__restrict__ la
       const int32_t R = __shfl(r, leader);
       const bool mine = todo && r == R;
       const long long c = __popcll(__ballot(mine));
-      long long s[3];
-      for (int d = 0; d < 3; ++d) s[d] = wave_sum(mine ? o[d] : 0ll);
+      long long sm[3];
+      for (int d = 0; d < 3; ++d) sm[d] = wave_sum(mine ? o[d] : 0ll);
       if (R != cur) {
-        flush();
+        if (cur >= 0 && lane == 0) flush(cur, acc);
         cur = R;
         acc[0] = acc[1] = acc[2] = acc[3] = 0;
       }
       acc[0] += c;
-      for (int d = 0; d < 3; ++d) acc[d + 1] += s[d];
+      for (int d = 0; d < 3; ++d) acc[d + 1] += sm[d];
       todo = todo && !mine;
     }
   }
-  flush();
-  if (lane == 0 && total) atomicAdd(dispersed, (unsigned long long)total);
+  if (lane == 0) {
+    s_root[wv] = cur;
+    for (int d = 0; d < 4; ++d) s_acc[wv][d] = acc[d];
+    s_total[wv] = total;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t r = -1;
+    long long v[4] = {0, 0, 0, 0};
+    long long t = 0;
+    for (int w = 0; w < STATS_WAVES; ++w) {
+      t += s_total[w];
+      if (s_root[w] < 0) continue;
+      if (s_root[w] != r) {
+        if (r >= 0) flush(r, v);
+        r = s_root[w];
+        v[0] = v[1] = v[2] = v[3] = 0;
+      }
+      for (int d = 0; d < 4; ++d) v[d] += s_acc[w][d];
+    }
+    if (r >= 0) flush(r, v);
+    if (t) atomicAdd(dispersed, (unsigned long long)t);
+  }
 }
 
 // Roots among the CHUNK nodes of each block.
@@ -546,21 +595,18 @@ int lb_droplets(lb_handle *h, lb_droplet_stats *stats, int32_t *label, int64_t c
   HIP_TRY(hipEventRecord(h->ana_ev[0], h->stream));
   rc = fields_to_arena(h, a);
   if (rc) return rc;
-  HIP_TRY(hipMemsetAsync(a.counters, 0, 8 * 4, h->stream));
   const int tiles = h->D == 2 ? tiles_x<2>(g) * tiles_y<2>(g) : tiles_x<3>(g) * tiles_y<3>(g) * tiles_z<3>(g);
   if (h->D == 2) {
-    hipLaunchKernelGGL(k_cc_local<2>, dim3(tiles), dim3(TPB), 0, h->stream, a.r1, a.r2, a.parent, a.vol,
-                       a.sums, g);
+    hipLaunchKernelGGL(k_cc_local<2>, dim3(tiles), dim3(TPB), 0, h->stream, a.r1, a.r2, a.parent, a.counters, g);
     hipLaunchKernelGGL(k_cc_border<2>, dim3(nb_nodes), dim3(TPB), 0, h->stream, a.parent, g);
   } else {
-    hipLaunchKernelGGL(k_cc_local<3>, dim3(tiles), dim3(TPB), 0, h->stream, a.r1, a.r2, a.parent, a.vol,
-                       a.sums, g);
+    hipLaunchKernelGGL(k_cc_local<3>, dim3(tiles), dim3(TPB), 0, h->stream, a.r1, a.r2, a.parent, a.counters, g);
     hipLaunchKernelGGL(k_cc_border<3>, dim3(nb_nodes), dim3(TPB), 0, h->stream, a.parent, g);
   }
-  hipLaunchKernelGGL(k_cc_flatten, dim3(nb_nodes), dim3(TPB), 0, h->stream, a.parent, g);
-  const int64_t waves = (h->N + 64 * STATS_ITER - 1) / (64 * STATS_ITER);
-  hipLaunchKernelGGL(k_cc_stats, dim3((int)((waves + TPB / 64 - 1) / (TPB / 64))), dim3(TPB), 0, h->stream,
-                     a.parent, a.vol, a.sums, g, a.counters + 1);
+  hipLaunchKernelGGL(k_cc_flatten, dim3(nb_nodes), dim3(TPB), 0, h->stream, a.parent, a.vol, a.sums, g);
+  const int64_t per_block = (int64_t)64 * STATS_ITER * STATS_WAVES;
+  hipLaunchKernelGGL(k_cc_stats, dim3((int)((h->N + per_block - 1) / per_block)), dim3(STATS_TPB), 0,
+                     h->stream, a.parent, a.vol, a.sums, g, a.counters + 1);
   hipLaunchKernelGGL(k_root_count, dim3(nb), dim3(TPB), 0, h->stream, a.parent, a.cnt, g);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, h->stream, a.cnt, a.off, nb, a.counters);
   hipLaunchKernelGGL(k_root_write, dim3(nb), dim3(TPB), 0, h->stream, a.parent, a.off, a.vol, a.sums, g,
