@@ -37,7 +37,8 @@ class _Params(C.Structure):
     _fields_ = [("lattice", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("walls_y", C.c_int32), ("tau", C.c_double), ("A_s", C.c_double),
                 ("beta", C.c_double), ("A_nci", C.c_double), ("h_min", C.c_double),
-                ("h_max", C.c_double), ("force", C.c_double * 3), ("tau2", C.c_double)]
+                ("h_max", C.c_double), ("force", C.c_double * 3), ("tau2", C.c_double),
+                ("nci_mode", C.c_int32)]
 
 
 def _load():
@@ -69,6 +70,8 @@ def _load():
         lib.lbo_collide_node.argtypes = [P(_Params), dp, dp, dp, dp, dp, dp]
         lib.lbo_A_h.argtypes = [C.c_double] * 4
         lib.lbo_A_h.restype = C.c_double
+        lib.lbo_A_h_shifted.argtypes = [C.c_double] * 4
+        lib.lbo_A_h_shifted.restype = C.c_double
         lib.lbo_node_nci.argtypes = [P(_Params), dp, C.c_int64, dp, ip, dp]
         _lib = lib
     return _lib
@@ -98,11 +101,12 @@ class Params:
     h_max: float = 4.0
     force: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
     tau2: float = 0.0
+    nci_mode: int = 0
 
     def to_c(self) -> _Params:
         p = _Params()
         for k in ("lattice", "nx", "ny", "nz", "walls_y", "tau", "A_s", "beta", "A_nci",
-                  "h_min", "h_max", "tau2"):
+                  "h_min", "h_max", "tau2", "nci_mode"):
             setattr(p, k, getattr(self, k))
         for a in range(3):
             p.force[a] = float(self.force[a])
@@ -150,6 +154,10 @@ def collide_node(p: Params, f1, f2, G, F):
 
 def A_h(h: float, A: float, h_min: float, h_max: float) -> float:
     return _load().lbo_A_h(float(h), float(A), float(h_min), float(h_max))
+
+
+def A_h_shifted(h: float, A: float, h_min: float, h_max: float) -> float:
+    return _load().lbo_A_h_shifted(float(h), float(A), float(h_min), float(h_max))
 
 
 def node_nci(p: Params, psi: np.ndarray, node: int):

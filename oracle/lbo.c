@@ -8,7 +8,10 @@
  *   3. G = 3 sum_i w_i c_i psi(x + c_i)   (second-order isotropic gradient)
  *      n = -G/|G|, delta_I = |G|/2
  *   4. NCI: h = first s in 1..floor(h_max) with psi(x + round(s n)) >= psi(x)
- *      (marching stops at a wall), A_h(h), F_rep = -A_h n delta_I (Eq. near_c)
+ *      (marching stops at a wall), A_h(h), F_rep = -A_h n delta_I (Eq. near_c).
+ *      Continuous-NCI variant (nci_mode 1): psi sampled at x + s n by
+ *      multilinear interpolation for s = 1..ceil(h_max), h refined to the
+ *      linear crossing point between the last two samples, shifted A_h.
  *   5. F = F_body + F_rep
  *   6-7. f = f1 + f2, u = j/rho; BGK + exact-difference forcing + perturbation
  *   8. Latva-Kokko recolouring
@@ -87,6 +90,14 @@ double lbo_A_h(double h, double A, double h_min, double h_max) {
   return 0.0;
 }
 
+double lbo_A_h_shifted(double h, double A, double h_min, double h_max) {
+  if (h <= h_min) return A;
+  if (h > h_max) return 0.0;
+  double r = (h_min / h) * (h_min / h) * (h_min / h);
+  double q = (h_min / h_max) * (h_min / h_max) * (h_min / h_max);
+  return A * (r - q) / (1.0 - q);
+}
+
 /* ---- collision at one node (BGK + EDM + perturbation, then recolour) ---- */
 static void collide(const lbo_params *p, int Q, int32_t (*c)[3], const double *w,
                     const double *f1, const double *f2, const double G[3],
@@ -152,6 +163,38 @@ static int64_t nb(const lbo_params *p, int x, int y, int z, int dx, int dy, int 
   return xx + (int64_t)p->nx * (yy + (int64_t)p->ny * zz);
 }
 
+/* psi at a continuous position: multilinear interpolation of the node values
+ * (lerp along x, then y, then z), wrapping along periodic axes; with walls
+ * the stencil rows are clamped into the fluid rows [1, ny-2], i.e. psi is
+ * extended beyond the fluid by the wall rows' copy rule. */
+static double psi_at(const lbo_params *p, const double *psi, int dim, const double pos[3]) {
+  int i0[3] = {0, 0, 0};
+  double t[3] = {0, 0, 0};
+  for (int a = 0; a < dim; ++a) {
+    double f = floor(pos[a]);
+    i0[a] = (int)f;
+    t[a] = pos[a] - f;
+  }
+  double cz[2] = {0, 0};
+  for (int kz = 0; kz < (dim == 3 ? 2 : 1); ++kz) {
+    double cy[2];
+    for (int ky = 0; ky < 2; ++ky) {
+      double cx[2];
+      for (int kx = 0; kx < 2; ++kx) {
+        int xx = wrap(i0[0] + kx, p->nx);
+        int yy = i0[1] + ky;
+        if (p->walls_y) yy = yy < 1 ? 1 : (yy > p->ny - 2 ? p->ny - 2 : yy);
+        else yy = wrap(yy, p->ny);
+        int zz = dim == 3 ? wrap(i0[2] + kz, p->nz) : 0;
+        cx[kx] = psi[xx + (int64_t)p->nx * (yy + (int64_t)p->ny * zz)];
+      }
+      cy[ky] = cx[0] + t[0] * (cx[1] - cx[0]);
+    }
+    cz[kz] = cy[0] + t[1] * (cy[1] - cy[0]);
+  }
+  return dim == 3 ? cz[0] + t[2] * (cz[1] - cz[0]) : cz[0];
+}
+
 /* gradient, NCI hit distance and F_rep at a fluid node; optionally the decision
  * margin (smallest |psi(y_s)-psi(x)| and distance of s*n to a rounding tie) */
 static void node_nci(const lbo_params *p, int Q, int32_t (*c)[3], const double *w,
@@ -167,7 +210,30 @@ static void node_nci(const lbo_params *p, int Q, int32_t (*c)[3], const double *
   Frep[0] = Frep[1] = Frep[2] = 0;
   *hit = 0;
   double mg = INFINITY;
-  if (p->A_nci > 0 && g > 0) {
+  if (p->A_nci > 0 && g > 0 && p->nci_mode == 1) {
+    /* continuous-NCI variant: first s with psi(x + s n) >= psi(x), h at the
+     * linear crossing between samples s-1 and s (h = 1 for s = 1) */
+    const int dim = p->lattice == LBO_D2Q9 ? 2 : 3;
+    double n[3] = {-G[0] / g, -G[1] / g, -G[2] / g};
+    int smax = (int)ceil(p->h_max);
+    double prev = psi[self], h = 0;
+    for (int s = 1; s <= smax; ++s) {
+      double pos[3] = {x + s * n[0], y + s * n[1], z + s * n[2]};
+      double ps = psi_at(p, psi, dim, pos);
+      double d = fabs(ps - psi[self]);
+      if (d < mg) mg = d;
+      if (ps >= psi[self]) {
+        *hit = s;
+        h = s == 1 ? 1.0 : (s - 1) + (psi[self] - prev) / (ps - prev);
+        break;
+      }
+      prev = ps;
+    }
+    if (*hit) {
+      double Ah = lbo_A_h_shifted(h, p->A_nci, p->h_min, p->h_max);
+      for (int a = 0; a < 3; ++a) Frep[a] = -Ah * n[a] * 0.5 * g;
+    }
+  } else if (p->A_nci > 0 && g > 0) {
     double n[3] = {-G[0] / g, -G[1] / g, -G[2] / g};
     int smax = (int)floor(p->h_max);
     for (int s = 1; s <= smax; ++s) {

@@ -48,6 +48,10 @@ typedef struct {
   double tau2;              /* relaxation time of component 2; 0: both use tau.
                                Otherwise tau is component 1's and the node's
                                1/tau_mix = (rho1/rho)/tau + (rho2/rho)/tau2  */
+  int32_t nci_mode;         /* 0: R-NCI (integer march, nearest-node samples,
+                               A_h of Eq. near_c); 1: continuous-NCI variant
+                               (interpolated samples, continuous h, A_h shifted
+                               to reach 0 at h_max)                          */
 } lbo_params;
 
 typedef struct lbo lbo;
@@ -95,6 +99,9 @@ void lbo_equilibrium(int lattice, double rho, const double u[3], double *feq);
 void lbo_collide_node(const lbo_params *p, const double *f1, const double *f2,
                       const double G[3], const double F[3], double *out1, double *out2);
 double lbo_A_h(double h, double A, double h_min, double h_max);
+/* continuous-NCI variant: A for h <= h_min, A ((h_min/h)^3 - q)/(1 - q) with
+ * q = (h_min/h_max)^3 up to h_max, 0 beyond (continuous at both ends) */
+double lbo_A_h_shifted(double h, double A, double h_min, double h_max);
 /* gradient and NCI at one node of a given psi field (N values, wall rows
  * already holding their copied values). */
 void lbo_node_nci(const lbo_params *p, const double *psi, int64_t node, double G[3],
