@@ -86,6 +86,17 @@ typedef struct {
                           a node relaxes at 1/tau_mix = (rho1/rho)/tau +
                           (rho2/rho)/tau2.  0 = one mixture tau (the paper's
                           model)                                              */
+  int32_t nci_mode;    /* 0: the integer NCI probe (h = first s in
+                          1..floor(h_max) with psi(x + round(s n)) >= psi(x),
+                          marching stopped by walls; A_h of Eq. near_c).
+                          1: continuous-NCI variant (not the paper's rule):
+                          psi sampled at x + s n, s = 1..ceil(h_max), by
+                          multilinear interpolation (rows clamped into the
+                          fluid with walls), h at the linear crossing of the
+                          last two samples (1 for s = 1), A_h shifted to
+                          A ((h_min/h)^3 - q)/(1 - q), q = (h_min/h_max)^3, so
+                          F_rep is continuous in the fields.  Other values
+                          are LB_EINVAL.                                      */
 } lb_params;
 
 /* Observables of the current state, accumulated in FP64 in a fixed order:
@@ -239,7 +250,8 @@ typedef struct lb_batch lb_batch;
 
 /* p: n parameter sets.  Creates n handles on the stream plus the tile tables
  * and persistent-launch groups.  Errors as lb_create, and LB_EINVAL when the
- * channels differ in lattice/storage/obs_every. */
+ * channels differ in lattice/storage/obs_every or ask for the continuous-NCI
+ * variant (nci_mode 1 runs on single lattices only). */
 int lb_batch_create(const lb_params *p, int32_t n, void *hip_stream, lb_batch **out);
 /* As lb_init_fields for channel c (0 <= c < n). */
 int lb_batch_init_fields(lb_batch *b, int32_t c, const double *rho1, const double *rho2,

@@ -63,14 +63,20 @@ void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0, hipE
   else hipLaunchKernelGGL(kernel, grid, block, 0, st, a);
 }
 
-template <int D, typename S, typename R, int SRC, int MODE>
-void launch_main(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+template <int D, typename S, typename R, int SRC, int MODE, int NCI>
+void launch_main_nci(lb_handle *h, const Args<S, R> &a, hipEvent_t e0, hipEvent_t e1) {
   const int nb = blocks_main(h);
   if constexpr (D == 2)
-    launch(k_main<D, S, R, SRC, MODE, BY2, TZ2, H2>, dim3(nb), dim3(64, BY2), h->stream, e0, e1, a);
+    launch(k_main<D, S, R, SRC, MODE, BY2, TZ2, H2, 1, NCI>, dim3(nb), dim3(64, BY2), h->stream, e0, e1, a);
   else
-    launch(k_main<D, S, R, SRC, MODE, BY3, TZ3, H3, LBNCI_WPE_MAIN3>, dim3(nb), dim3(64, BY3), h->stream,
-           e0, e1, a);
+    launch(k_main<D, S, R, SRC, MODE, BY3, TZ3, H3, LBNCI_WPE_MAIN3, NCI>, dim3(nb), dim3(64, BY3),
+           h->stream, e0, e1, a);
+}
+
+template <int D, typename S, typename R, int SRC, int MODE>
+void launch_main(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (h->p.nci_mode == 1) launch_main_nci<D, S, R, SRC, MODE, 1>(h, a, e0, e1);
+  else launch_main_nci<D, S, R, SRC, MODE, 0>(h, a, e0, e1);
 }
 
 template <int D, typename S, typename R, int SRC>
@@ -155,6 +161,7 @@ int validate(const lb_params *p) {
     return fail(LB_EINVAL, "lattice too large (at most 2^29 nodes)");
   if (!(p->tau > 0.5)) return fail(LB_EINVAL, "tau must exceed 1/2");
   if (!(p->tau2 == 0.0 || p->tau2 > 0.5)) return fail(LB_EINVAL, "tau2 must be 0 or exceed 1/2");
+  if (p->nci_mode != 0 && p->nci_mode != 1) return fail(LB_EINVAL, "nci_mode must be 0 or 1");
   if (!(p->beta >= 0.0 && p->beta <= 1.0)) return fail(LB_EINVAL, "beta must lie in [0,1]");
   if (!(p->A_s >= 0.0)) return fail(LB_EINVAL, "A_s must be >= 0");
   if (!(p->A_nci >= 0.0)) return fail(LB_EINVAL, "A_nci must be >= 0");

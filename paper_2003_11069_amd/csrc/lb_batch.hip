@@ -407,6 +407,8 @@ int lb_batch_create(const lb_params *p, int32_t n, void *hip_stream, lb_batch **
     if (p[c].lattice != p[0].lattice || p[c].storage != p[0].storage)
       return fail(LB_EINVAL, "all channels of a batch share lattice and storage");
     if (p[c].obs_every != p[0].obs_every) return fail(LB_EINVAL, "all channels share obs_every");
+    if (p[c].nci_mode != 0)
+      return fail(LB_EINVAL, "channel %d: batches run the integer NCI probe only (nci_mode 0)", c);
   }
   lb_batch *b = new (std::nothrow) lb_batch();
   if (!b) return fail(LB_ENOMEM, "host allocation failed");

@@ -118,6 +118,7 @@ inline lbk::Args<S, R> make_args(lb_handle *h, int in, int out) {
   a.h_max = (R)p.h_max;
   for (int d = 0; d < 3; ++d) a.F[d] = (R)p.force[d];
   a.smax = (int)std::floor(p.h_max);
+  a.smaxc = (int)std::ceil(p.h_max);
   a.in = lbk::State<S, R>{(S *)h->s[in], h->s0[in], (R *)h->a[in], h->B[in]};
   a.out = lbk::State<S, R>{(S *)h->s[out], h->s0[out], (R *)h->a[out], h->B[out]};
   a.xt = h->xt;

@@ -110,6 +110,7 @@ struct Args {
   int two_tau;
   R F[3];
   int smax;           // floor(h_max)
+  int smaxc;          // ceil(h_max), probe steps of the continuous-NCI variant
   State<S, R> in, out;
   const double *xt;   // explicit first-step state: f_i/w_i - 1 (Q*N) or null
   const double *xc;   // explicit first-step state: f1_i/w_i (Q*N)
@@ -385,6 +386,17 @@ __device__ __forceinline__ R strength(int h, R A, R hmin, R hmax) {
   return (R)0;
 }
 
+// Continuous-NCI variant: A below h_min, A ((h_min/h)^3 - q)/(1 - q) with
+// q = (h_min/h_max)^3 up to h_max (0 there), 0 beyond.
+template <typename R>
+__device__ __forceinline__ R strength_shifted(R h, R A, R hmin, R hmax) {
+  if (h <= hmin) return A;
+  if (h > hmax) return (R)0;
+  const R r = (hmin / h) * (hmin / h) * (hmin / h);
+  const R q = (hmin / hmax) * (hmin / hmax) * (hmin / hmax);
+  return A * (r - q) / ((R)1 - q);
+}
+
 __device__ __forceinline__ double round_away(double v) { return round(v); }
 __device__ __forceinline__ float round_away(float v) { return roundf(v); }
 
@@ -414,7 +426,7 @@ __device__ __forceinline__ void main_decode(int nx, int ny, int lb, int &bx, int
   bz = lb / (gx * gy);
 }
 
-template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H>
+template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int NCI = 0>
 __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, int bz, int slot,
                                           R *tile, double (*red)[8]) {
   using L = Lat<D>;
@@ -472,7 +484,51 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
     // near-contact probe along n = -G^: first s with psi(x + round(s n)) >= psi(x)
     R Fr[3] = {0, 0, 0};
     int hit = 0;
-    if (A.A > (R)0 && g > (R)0) {
+    if (NCI == 1 && A.A > (R)0 && g > (R)0) {
+      // continuous-NCI variant: psi at x + s n by multilinear interpolation
+      // (lerp x, then y, then z), h at the linear crossing between samples
+      // s-1 and s (h = 1 for s = 1), A_h shifted to reach 0 at h_max
+      const R ps = T(0, 0, 0);
+      const R nn[3] = {-Gh[0], -Gh[1], -Gh[2]};
+      auto node_psi = [&](int ox, int oy, int oz) -> R {
+        if (abs(ox) <= H && abs(oy) <= H && abs(oz) <= H) return T(ox, oy, oz);
+        const int xt = wrapi(x + ox, A.nx);
+        int yt = y + oy;
+        if (A.walls) yt = yt < 1 ? 1 : (yt > A.ny - 2 ? A.ny - 2 : yt);
+        else yt = wrapi(yt, A.ny);
+        const int zt = (D == 3) ? wrapi(z + oz, A.nz) : 0;
+        return ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)yt + (uint32_t)A.ny * zt));
+      };
+      R prev = ps, hc = 0;
+      for (int s = 1; s <= A.smaxc; ++s) {
+        const R px = (R)s * nn[0], py = (R)s * nn[1], pz = (D == 3) ? (R)s * nn[2] : (R)0;
+        const R fx = floor(px), fy = floor(py), fz = floor(pz);
+        const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+        const R tx = px - fx, ty = py - fy, tzz = pz - fz;
+        R cz[2] = {0, 0};
+        for (int kz = 0; kz < (D == 3 ? 2 : 1); ++kz) {
+          R cy[2];
+          for (int ky = 0; ky < 2; ++ky) {
+            const R a0 = node_psi(ix, iy + ky, iz + kz), a1 = node_psi(ix + 1, iy + ky, iz + kz);
+            cy[ky] = a0 + tx * (a1 - a0);
+          }
+          cz[kz] = cy[0] + ty * (cy[1] - cy[0]);
+        }
+        const R pv = (D == 3) ? cz[0] + tzz * (cz[1] - cz[0]) : cz[0];
+        if (pv >= ps) {
+          hit = s;
+          hc = (s == 1) ? (R)1 : (R)(s - 1) + (ps - prev) / (pv - prev);
+          break;
+        }
+        prev = pv;
+      }
+      if (hit) {
+        const R Ah = strength_shifted<R>(hc, A.A, A.h_min, A.h_max);
+        Fr[0] = -Ah * nn[0] * (R)0.5 * g;
+        Fr[1] = -Ah * nn[1] * (R)0.5 * g;
+        Fr[2] = -Ah * nn[2] * (R)0.5 * g;
+      }
+    } else if (NCI == 0 && A.A > (R)0 && g > (R)0) {
       const R ps = T(0, 0, 0);
       const R nn[3] = {-Gh[0], -Gh[1], -Gh[2]};
       for (int s = 1; s <= A.smax; ++s) {
@@ -649,14 +705,15 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
   }
 }
 
-// k_main: one main tile per block over a single lattice.
-template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int WPE = 1>
+// k_main: one main tile per block over a single lattice (NCI: 0 the integer
+// probe, 1 the continuous-NCI variant).
+template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int WPE = 1, int NCI = 0>
 __global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void k_main(Args<S, R> A) {
   __shared__ R tile[MainTile<D, BY, TZ, H>::TS];
   __shared__ double red[BY][8];
   int bx, by, bz;
   main_decode<D, BY>(A.nx, A.ny, logical_block(blockIdx.x, gridDim.x, A.xcd_remap), bx, by, bz);
-  main_tile<D, S, R, SRC, MODE, BY, TZ, H>(A, bx, by, bz, blockIdx.x, tile, red);
+  main_tile<D, S, R, SRC, MODE, BY, TZ, H, NCI>(A, bx, by, bz, blockIdx.x, tile, red);
 }
 
 

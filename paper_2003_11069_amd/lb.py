@@ -36,7 +36,8 @@ class lb_params(C.Structure):
                 ("beta", C.c_double), ("A_nci", C.c_double), ("h_min", C.c_double),
                 ("h_max", C.c_double), ("force", C.c_double * 3), ("storage", C.c_int32),
                 ("obs_every", C.c_int32), ("conv_window", C.c_int32), ("conv_m", C.c_int32),
-                ("conv_eps", C.c_double), ("tau2", C.c_double)]
+                ("conv_eps", C.c_double), ("tau2", C.c_double),
+                ("nci_mode", C.c_int32)]
 
 
 class lb_obs(C.Structure):
@@ -169,6 +170,7 @@ class Params:
     conv_m: int = 3
     conv_eps: float = 1e-4
     tau2: float = 0.0
+    nci_mode: int = 0
 
     @classmethod
     def from_dict(cls, d: dict, **kw):

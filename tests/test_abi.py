@@ -54,7 +54,7 @@ def test_lattice_tables(lat, Q):
 BAD = [dict(tau=0.5), dict(tau=0.3), dict(beta=1.5), dict(beta=-0.1), dict(nx=0), dict(nz=2),
        dict(h_min=5.0, h_max=4.0), dict(h_max=4.5), dict(h_min=0.0), dict(A_nci=-1.0),
        dict(storage=7), dict(lattice=5), dict(walls_y=1, ny=2), dict(A_s=-0.1), dict(tau2=0.4),
-       dict(tau2=-1.0)]
+       dict(tau2=-1.0), dict(nci_mode=2), dict(nci_mode=-1)]
 
 
 @pytest.mark.parametrize("bad", BAD)
@@ -62,6 +62,14 @@ def test_create_rejects_invalid(bad):
     with pytest.raises(P.LBError) as ei:
         P.Lattice(P.Params(**bad))
     assert ei.value.code == -1
+
+
+def test_batch_rejects_continuous_nci():
+    """Batches run the integer probe only; the check precedes any device call."""
+    ps = [P.Params(nx=64, ny=32), P.Params(nx=64, ny=32, nci_mode=1)]
+    with pytest.raises(P.LBError) as ei:
+        P.Batch(ps)
+    assert ei.value.code == -1 and "nci_mode" in str(ei.value)
 
 
 def test_last_error_message():
