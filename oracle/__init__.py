@@ -58,6 +58,8 @@ def _load():
         lib.lbo_nodes.restype = C.c_int64
         lib.lbo_time.argtypes = [C.c_void_p]
         lib.lbo_time.restype = C.c_int64
+        lib.lbo_set_geometry.argtypes = [C.c_void_p, C.POINTER(C.c_uint8), dp, dp, dp]
+        lib.lbo_set_geometry.restype = C.c_int
         lib.lbo_init_fields.argtypes = [C.c_void_p, dp, dp, dp]
         lib.lbo_init_fields.restype = C.c_int
         lib.lbo_set_populations.argtypes = [C.c_void_p, dp, dp]
@@ -119,6 +121,9 @@ class Params:
     @property
     def N(self) -> int:
         return self.nx * self.ny * self.nz
+
+
+FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
 
 
 def lattice(lat: int):
@@ -194,6 +199,19 @@ class Oracle:
     @property
     def t(self) -> int:
         return self._lib.lbo_time(self._h)
+
+    def set_geometry(self, node_type, rho1, rho2, u=None):
+        """Node types (FLUID/SOLID/INLET/OUTLET, N bytes); inlet nodes take
+        rho1, rho2, u at their index.  Call before init_fields."""
+        t = np.ascontiguousarray(node_type, np.uint8).ravel()
+        r1 = np.ascontiguousarray(rho1, np.float64).ravel()
+        r2 = np.ascontiguousarray(rho2, np.float64).ravel()
+        uu = None if u is None else np.ascontiguousarray(u, np.float64).ravel()
+        assert t.size == self.N and r1.size == self.N and r2.size == self.N
+        rc = self._lib.lbo_set_geometry(self._h, t.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(r1),
+                                        _dp(r2), None if uu is None else _dp(uu))
+        if rc != 0:
+            raise ValueError("invalid geometry")
 
     def init_fields(self, rho1, rho2, u=None):
         r1 = np.ascontiguousarray(rho1, np.float64).ravel()

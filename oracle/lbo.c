@@ -16,6 +16,16 @@
  *   6-7. f = f1 + f2, u = j/rho; BGK + exact-difference forcing + perturbation
  *   8. Latva-Kokko recolouring
  *   9. pull streaming with half-way bounce-back at wall rows
+ * Geometry (lbo_set_geometry): a node-type mask on the periodic lattice.
+ * Solid nodes reflect (half-way bounce-back) and carry psi = the w_i-weighted
+ * mean of their non-solid neighbours (neutral wetting).  Inlet and outlet
+ * nodes each have a feeder: their first fluid neighbour along -x, +x, -y, +y,
+ * -z, +z.  After every collision an inlet takes the equilibrium at its
+ * prescribed velocity and composition with the feeder's density (a velocity
+ * inlet); an outlet takes the equilibrium at its prescribed density with the
+ * feeder's velocity and composition (a pressure outlet).  Their fluid
+ * neighbours then pull from them as from any node.  psi: inlets their
+ * prescribed composition, outlets their feeder's.
  * Parity pins: tests/test_oracle_units.py and tests/test_oracle_physics.py.
  */
 #include "lbo.h"
@@ -35,6 +45,9 @@ struct lbo {
   double *f1, *f2;   /* state at time t: [i][node]                 */
   double *g1, *g2;   /* post-collision scratch                     */
   double *psi;       /* order parameter (walls carry copied value) */
+  uint8_t *type;     /* node types (lbo_set_geometry) or NULL       */
+  double *in1, *in2, *inu; /* prescribed rho1, rho2 (N) and u (3N)  */
+  int64_t *feeder;   /* fluid neighbour of each inlet/outlet (N)    */
 };
 
 /* ---- lattice (D2Q9 / D3Q27), weights by |c|^2 ----------------------- */
@@ -198,8 +211,8 @@ static double psi_at(const lbo_params *p, const double *psi, int dim, const doub
 /* gradient, NCI hit distance and F_rep at a fluid node; optionally the decision
  * margin (smallest |psi(y_s)-psi(x)| and distance of s*n to a rounding tie) */
 static void node_nci(const lbo_params *p, int Q, int32_t (*c)[3], const double *w,
-                     const double *psi, int x, int y, int z, double G[3], int32_t *hit,
-                     double Frep[3], double *margin) {
+                     const double *psi, const uint8_t *type, int x, int y, int z, double G[3],
+                     int32_t *hit, double Frep[3], double *margin) {
   int64_t self = x + (int64_t)p->nx * (y + (int64_t)p->ny * z);
   G[0] = G[1] = G[2] = 0;
   for (int i = 0; i < Q; ++i) {
@@ -246,6 +259,8 @@ static void node_nci(const lbo_params *p, int Q, int32_t (*c)[3], const double *
       }
       if (is_wall_y(p, y + off[1]) || (p->walls_y && (y + off[1] < 0 || y + off[1] >= p->ny)))
         break; /* the probe stops at a wall: no facing interface */
+      if (type && type[nb(p, x, y, z, off[0], off[1], off[2])] != LBO_FLUID)
+        break; /* ... and at any node that is not fluid */
       double py = psi[nb(p, x, y, z, off[0], off[1], off[2])];
       double d = fabs(py - psi[self]);
       if (d < mg) mg = d;
@@ -271,7 +286,7 @@ void lbo_node_nci(const lbo_params *p, const double *psi, int64_t node, double G
   int x = (int)(node % p->nx);
   int y = (int)((node / p->nx) % p->ny);
   int z = (int)(node / ((int64_t)p->nx * p->ny));
-  node_nci(p, Q, c, w, psi, x, y, z, G, hit, Frep, NULL);
+  node_nci(p, Q, c, w, psi, NULL, x, y, z, G, hit, Frep, NULL);
 }
 
 /* ---- handle ---------------------------------------------------------------- */
@@ -290,9 +305,52 @@ lbo *lbo_create(const lbo_params *p) {
   return h;
 }
 
+/* first fluid neighbour of node n along -x, +x, -y, +y, -z, +z, or -1 */
+static int64_t find_feeder(const lbo_params *p, const uint8_t *type, int64_t n) {
+  static const int d[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+  int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
+  for (int k = 0; k < 6; ++k) {
+    if (p->nz == 1 && d[k][2] != 0) continue;
+    int64_t m = nb(p, x, y, z, d[k][0], d[k][1], d[k][2]);
+    if (type[m] == LBO_FLUID) return m;
+  }
+  return -1;
+}
+
+int lbo_set_geometry(lbo *h, const uint8_t *type, const double *rho1, const double *rho2,
+                     const double *u) {
+  const lbo_params *p = &h->p;
+  if (p->walls_y || p->nci_mode != 0) return -1;
+  for (int64_t n = 0; n < h->N; ++n) {
+    if (type[n] > LBO_OUTLET) return -1;
+    if (type[n] == LBO_INLET || type[n] == LBO_OUTLET) {
+      if (find_feeder(p, type, n) < 0) return -1;
+      if (!(rho1[n] >= 0 && rho2[n] >= 0 && rho1[n] + rho2[n] > 0)) return -1;
+    }
+  }
+  free(h->type); free(h->in1); free(h->in2); free(h->inu); free(h->feeder);
+  h->type = (uint8_t *)malloc((size_t)h->N);
+  memcpy(h->type, type, (size_t)h->N);
+  h->in1 = (double *)calloc((size_t)h->N, sizeof(double));
+  h->in2 = (double *)calloc((size_t)h->N, sizeof(double));
+  h->inu = (double *)calloc(3 * (size_t)h->N, sizeof(double));
+  h->feeder = (int64_t *)malloc(sizeof(int64_t) * (size_t)h->N);
+  for (int64_t n = 0; n < h->N; ++n) {
+    h->feeder[n] = -1;
+    if (type[n] != LBO_INLET && type[n] != LBO_OUTLET) continue;
+    h->feeder[n] = find_feeder(p, type, n);
+    h->in1[n] = rho1[n];
+    h->in2[n] = rho2[n];
+    if (u && type[n] == LBO_INLET)
+      for (int a = 0; a < h->dim; ++a) h->inu[a * h->N + n] = u[a * h->N + n];
+  }
+  return 0;
+}
+
 void lbo_destroy(lbo *h) {
   if (!h) return;
   free(h->f1); free(h->f2); free(h->g1); free(h->g2); free(h->psi);
+  free(h->type); free(h->in1); free(h->in2); free(h->inu); free(h->feeder);
   free(h);
 }
 
@@ -301,13 +359,17 @@ int64_t lbo_time(const lbo *h) { return h->t; }
 
 static int node_y(const lbo *h, int64_t n) { return (int)((n / h->p.nx) % h->p.ny); }
 
+static int is_fluid(const lbo *h, int64_t n) {
+  return h->type ? h->type[n] == LBO_FLUID : !is_wall_y(&h->p, node_y(h, n));
+}
+
 int lbo_init_fields(lbo *h, const double *rho1, const double *rho2, const double *u) {
   for (int64_t n = 0; n < h->N; ++n) {
-    if (is_wall_y(&h->p, node_y(h, n))) continue;
+    if (!is_fluid(h, n)) continue;
     if (!(rho1[n] >= 0) || !(rho2[n] >= 0) || !(rho1[n] + rho2[n] > 0)) return -1;
   }
   for (int64_t n = 0; n < h->N; ++n) {
-    int wall = is_wall_y(&h->p, node_y(h, n));
+    int wall = !is_fluid(h, n);
     double un[3] = {0, 0, 0};
     if (u)
       for (int a = 0; a < h->dim; ++a) un[a] = u[a * h->N + n];
@@ -322,7 +384,7 @@ int lbo_init_fields(lbo *h, const double *rho1, const double *rho2, const double
 
 void lbo_set_populations(lbo *h, const double *f1, const double *f2) {
   for (int64_t n = 0; n < h->N; ++n) {
-    int wall = is_wall_y(&h->p, node_y(h, n));
+    int wall = !is_fluid(h, n);
     for (int i = 0; i < h->Q; ++i) {
       h->f1[i * h->N + n] = wall ? 0.0 : f1[i * h->N + n];
       h->f2[i * h->N + n] = wall ? 0.0 : f2[i * h->N + n];
@@ -340,13 +402,34 @@ static void compute_psi(lbo *h) {
   const lbo_params *p = &h->p;
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < h->N; ++n) {
-    if (is_wall_y(p, node_y(h, n))) continue;
+    if (!is_fluid(h, n)) continue;
     double r1 = 0, r2 = 0;
     for (int i = 0; i < h->Q; ++i) {
       r1 += h->f1[i * h->N + n];
       r2 += h->f2[i * h->N + n];
     }
     h->psi[n] = (r1 - r2) / (r1 + r2);
+  }
+  if (h->type) {
+    /* inlets: their prescribed composition; outlets: their feeder's psi */
+    for (int64_t n = 0; n < h->N; ++n) {
+      if (h->type[n] == LBO_INLET) h->psi[n] = (h->in1[n] - h->in2[n]) / (h->in1[n] + h->in2[n]);
+      else if (h->type[n] == LBO_OUTLET) h->psi[n] = h->psi[h->feeder[n]];
+    }
+    /* solids: w_i-weighted mean of the non-solid neighbours (0 without any) */
+    for (int64_t n = 0; n < h->N; ++n) {
+      if (h->type[n] != LBO_SOLID) continue;
+      int x = (int)(n % p->nx), y = node_y(h, n), z = (int)(n / ((int64_t)p->nx * p->ny));
+      double sw = 0, sp = 0;
+      for (int i = 0; i < h->Q; ++i) {
+        if (h->c[i][0] == 0 && h->c[i][1] == 0 && h->c[i][2] == 0) continue;
+        int64_t m = nb(p, x, y, z, h->c[i][0], h->c[i][1], h->c[i][2]);
+        if (h->type[m] == LBO_SOLID) continue;
+        sw += h->w[i];
+        sp += h->w[i] * h->psi[m];
+      }
+      h->psi[n] = sw > 0 ? sp / sw : 0.0;
+    }
   }
   if (p->walls_y) {
     for (int z = 0; z < p->nz; ++z)
@@ -362,7 +445,7 @@ static void compute_psi(lbo *h) {
 /* total force at a fluid node of the current state (psi already computed) */
 static void node_force(lbo *h, int x, int y, int z, double G[3], double F[3], int32_t *hit,
                        double Frep[3], double *margin) {
-  node_nci(&h->p, h->Q, h->c, h->w, h->psi, x, y, z, G, hit, Frep, margin);
+  node_nci(&h->p, h->Q, h->c, h->w, h->psi, h->type, x, y, z, G, hit, Frep, margin);
   for (int a = 0; a < 3; ++a) F[a] = h->p.force[a] + Frep[a];
   if (h->dim == 2) F[2] = 0.0;
 }
@@ -376,7 +459,7 @@ static void step_once(lbo *h) {
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < N; ++n) {
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
-    if (is_wall_y(p, y)) continue;
+    if (!is_fluid(h, n)) continue;
     double G[3], F[3], Frep[3];
     int32_t hit;
     node_force(h, x, y, z, G, F, &hit, Frep, NULL);
@@ -391,11 +474,57 @@ static void step_once(lbo *h) {
       h->g2[i * N + n] = o2[i];
     }
   }
+  /* open boundaries: post-collision state of inlet and outlet nodes from
+   * their feeders' post-collision populations */
+  if (h->type) {
+    for (int64_t n = 0; n < N; ++n) {
+      if (h->type[n] != LBO_INLET && h->type[n] != LBO_OUTLET) continue;
+      const int64_t f = h->feeder[n];
+      double r1 = 0, r2 = 0, j[3] = {0, 0, 0};
+      for (int i = 0; i < Q; ++i) {
+        double a = h->g1[i * N + f], b = h->g2[i * N + f];
+        r1 += a;
+        r2 += b;
+        for (int d = 0; d < 3; ++d) j[d] += h->c[i][d] * (a + b);
+      }
+      double rho = r1 + r2, e1, e2, ub[3];
+      if (h->type[n] == LBO_INLET) {
+        /* prescribed velocity and composition, the feeder's density */
+        double fr = h->in1[n] / (h->in1[n] + h->in2[n]);
+        e1 = rho * fr;
+        e2 = rho - e1;
+        for (int d = 0; d < 3; ++d) ub[d] = d < h->dim ? h->inu[d * N + n] : 0.0;
+      } else {
+        /* prescribed density, the feeder's velocity and composition */
+        double ro = h->in1[n] + h->in2[n];
+        e1 = ro * (r1 / rho);
+        e2 = ro - e1;
+        for (int d = 0; d < 3; ++d) ub[d] = j[d] / rho;
+      }
+      for (int i = 0; i < Q; ++i) {
+        h->g1[i * N + n] = equilibrium_i(h->w[i], h->c[i], e1, ub);
+        h->g2[i * N + n] = equilibrium_i(h->w[i], h->c[i], e2, ub);
+      }
+    }
+  }
   /* step 9: pull streaming, half-way bounce-back from wall rows */
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < N; ++n) {
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
-    if (is_wall_y(p, y)) continue;
+    if (!is_fluid(h, n)) continue;
+    if (h->type) {
+      for (int i = 0; i < Q; ++i) {
+        int64_t src = nb(p, x, y, z, -h->c[i][0], -h->c[i][1], -h->c[i][2]);
+        if (h->type[src] == LBO_SOLID) { /* half-way bounce-back */
+          h->f1[i * N + n] = h->g1[h->opp[i] * N + n];
+          h->f2[i * N + n] = h->g2[h->opp[i] * N + n];
+        } else {
+          h->f1[i * N + n] = h->g1[i * N + src];
+          h->f2[i * N + n] = h->g2[i * N + src];
+        }
+      }
+      continue;
+    }
     for (int i = 0; i < Q; ++i) {
       int ys = y - h->c[i][1];
       if (p->walls_y && is_wall_y(p, ys)) {
@@ -433,7 +562,7 @@ void lbo_fields(lbo *h, double *rho1, double *rho2, double *u) {
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < h->N; ++n) {
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
-    if (is_wall_y(p, y)) {
+    if (!is_fluid(h, n)) {
       rho1[n] = rho2[n] = 0;
       for (int a = 0; a < h->dim; ++a) u[a * h->N + n] = 0;
       continue;
@@ -454,7 +583,7 @@ void lbo_observables(lbo *h, double out[8]) {
   for (int k = 0; k < 8; ++k) out[k] = 0;
   for (int64_t n = 0; n < h->N; ++n) { /* fixed index order */
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
-    if (is_wall_y(p, y)) continue;
+    if (!is_fluid(h, n)) continue;
     double r1, r2, j[3], G[3], F[3], Frep[3], uu = 0, ux;
     int32_t hit;
     node_moments(h, n, &r1, &r2, j);
@@ -485,7 +614,7 @@ void lbo_diagnostics(lbo *h, double *psi, double *G, double *Frep, int32_t *hit,
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
     double g[3] = {0, 0, 0}, F[3], fr[3] = {0, 0, 0}, mg = INFINITY;
     int32_t ht = 0;
-    if (!is_wall_y(p, y)) node_force(h, x, y, z, g, F, &ht, fr, &mg);
+    if (is_fluid(h, n)) node_force(h, x, y, z, g, F, &ht, fr, &mg);
     for (int a = 0; a < 3; ++a) {
       G[a * h->N + n] = g[a];
       Frep[a * h->N + n] = fr[a];

@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 enum { LBO_D2Q9 = 0, LBO_D3Q27 = 1 };
+enum { LBO_FLUID = 0, LBO_SOLID = 1, LBO_INLET = 2, LBO_OUTLET = 3 };
 
 typedef struct {
   int32_t lattice;          /* LBO_D2Q9 or LBO_D3Q27                         */
@@ -62,6 +63,14 @@ int lbo_lattice(int lattice, int32_t *c, double *w, int32_t *opp);
 lbo *lbo_create(const lbo_params *p);
 void lbo_destroy(lbo *h);
 int64_t lbo_nodes(const lbo *h);
+
+/* Node types (N bytes, LBO_*) on the periodic lattice; requires walls_y = 0
+ * and nci_mode = 0.  Every inlet/outlet needs a fluid neighbour along an axis
+ * (its feeder).  Inlets take their composition rho1/(rho1+rho2) and velocity
+ * u (dim*N, may be NULL) at their index, outlets their density rho1 + rho2.
+ * Call before init_fields.  Returns 0, or -1 on an invalid mask. */
+int lbo_set_geometry(lbo *h, const uint8_t *type, const double *rho1, const double *rho2,
+                     const double *u);
 
 /* f_i^k(x,0) = E_i(rho^k(x), u(x)); u may be NULL (u = 0).  u layout: dim
  * component-major blocks of N.  Returns 0 or -1 on invalid densities. */

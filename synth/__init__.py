@@ -327,3 +327,103 @@ def two_layer_channel(nx=4, ny=34, y_i=16.5, tau1=1.0, tau2=2.0, force=1e-6, **k
     p = base_params(lattice=0, nx=nx, ny=ny, nz=1, walls_y=1, tau=tau1, tau2=tau2, A_nci=0.0,
                     force=(force, 0.0, 0.0), **kw)
     return Case(p, r1, r2)
+
+
+# --- node-type geometries (fluid 0, solid 1, inlet 2, outlet 3) --------------
+# Boundary conditions live in the library and the oracle; these only lay out
+# the mask and the inlet values (carried in rho1, rho2, u at inlet nodes).
+
+FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
+
+
+def solid_wall_channel(nx=40, ny=34, force=1e-6, tau=1.0, two_phase=False, seed=0) -> Case:
+    """Rows y = 0 and ny-1 solid on the periodic lattice (the walls_y channel
+    expressed as a mask); single phase unless ``two_phase``."""
+    t = np.zeros((ny, nx), np.uint8)
+    t[0] = t[-1] = SOLID
+    if two_phase:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        psi = np.tanh(3.0 * rng.uniform(-1, 1, (ny, nx))).ravel()
+        r1, r2 = _profile(psi)
+    else:
+        r1, r2 = np.ones(nx * ny), np.zeros(nx * ny)
+    p = base_params(nx=nx, ny=ny, tau=tau, force=(force, 0.0, 0.0))
+    return Case(p, r1, r2, None, {"type": t.ravel()})
+
+
+def obstacle_box(nx=64, ny=48, lattice=0, nz=1, seed=1, A_nci=0.01) -> Case:
+    """Closed periodic box with solid walls at y = 0, ny-1 and two solid
+    blocks, random two-phase fields, no driving (mass must be conserved)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.zeros((nz, ny, nx), np.uint8)
+    t[:, 0] = t[:, -1] = SOLID
+    t[:, ny // 4:ny // 4 + 6, nx // 5:nx // 5 + 9] = SOLID
+    t[:, ny // 2:ny // 2 + 10, (3 * nx) // 5:(3 * nx) // 5 + 5] = SOLID
+    psi = np.tanh(3.0 * rng.uniform(-1, 1, (nz, ny, nx))).ravel()
+    r1, r2 = _profile(psi)
+    p = base_params(lattice=lattice, nx=nx, ny=ny, nz=nz, A_nci=A_nci)
+    return Case(p, r1, r2, None, {"type": t.ravel()})
+
+
+def inlet_outlet_channel(nx=48, ny=26, u_in=0.01, tau=1.0, rho1_in=1.0, rho2_in=0.0) -> Case:
+    """Solid rows y = 0, ny-1; inlet column x = 0 with a plug velocity
+    (u_in, 0); outlet column x = nx-1."""
+    t = np.zeros((ny, nx), np.uint8)
+    t[:, 0] = INLET
+    t[:, -1] = OUTLET
+    t[0] = t[-1] = SOLID
+    N = nx * ny
+    r1 = np.full(N, rho1_in)
+    r2 = np.full(N, rho2_in)
+    u = np.zeros((2, N))
+    u[0, t.ravel() == INLET] = u_in
+    p = base_params(nx=nx, ny=ny, tau=tau, A_nci=0.0)
+    return Case(p, r1, r2, u, {"type": t.ravel(), "u_in": u_in})
+
+
+def flow_focuser_2d(scale=1.0, phi=1.0, u_c=0.005, tau=1.0, A_s=0.05, N_c=0.1, h_min=2.0,
+                    W_out=None, L_out=None) -> Case:
+    """2-D flow-focuser (Fig. 1 layout): a horizontal dispersed-phase inlet
+    channel of width H, two vertical continuous-phase inlet channels of width
+    H entering from the bottom and top, a striction of width h = H/2, and an
+    outlet channel (width ``W_out``, default 2h) ending in an outlet column.
+    Lattice units at scale 1: H = 16 (the paper's 200 um), h = 8.  Inlet
+    speeds u_c (continuous, both vertical inlets) and u_d = 2 phi u_c
+    (dispersed); A = N_c sigma / h_min with sigma = 2 A_s tau / 9."""
+    H = int(round(16 * scale))
+    h = max(4, int(round(8 * scale)))
+    W_out = 2 * h if W_out is None else W_out
+    L_in = 2 * H                       # dispersed inlet channel length
+    L_o = max(2, h)                    # striction length
+    L_out = 10 * H if L_out is None else L_out
+    ny = H + 2 * H + 2                 # vertical inlets (length H) above and below the junction
+    ny = max(ny, W_out + 2)
+    nx = 1 + L_in + H + L_o + L_out
+    yc = ny // 2
+    t = np.full((ny, nx), SOLID, np.uint8)
+    y0, y1 = yc - H // 2, yc - H // 2 + H            # dispersed channel rows [y0, y1)
+    xj = 1 + L_in                                    # junction columns [xj, xj + H)
+    t[y0:y1, 0:xj] = FLUID
+    t[1:ny - 1, xj:xj + H] = FLUID                   # vertical channels through the junction
+    ho0 = yc - h // 2
+    t[ho0:ho0 + h, xj + H:xj + H + L_o] = FLUID      # striction
+    wo0 = yc - W_out // 2
+    t[wo0:wo0 + W_out, xj + H + L_o:nx] = FLUID      # outlet channel
+    t[y0:y1, 0] = INLET
+    t[0, xj:xj + H] = INLET
+    t[ny - 1, xj:xj + H] = INLET
+    t[wo0:wo0 + W_out, nx - 1] = OUTLET
+    N = nx * ny
+    T = t.ravel()
+    r1 = np.zeros((ny, nx)); r2 = np.ones((ny, nx))
+    r1[y0:y1, 0:xj] = 1.0; r2[y0:y1, 0:xj] = 0.0     # dispersed phase fills its inlet channel
+    u = np.zeros((2, ny, nx))
+    u_d = 2.0 * phi * u_c
+    u[0, y0:y1, 0] = u_d
+    u[1, 0, xj:xj + H] = u_c
+    u[1, ny - 1, xj:xj + H] = -u_c
+    sigma = 2.0 * A_s * tau / 9.0
+    p = base_params(nx=nx, ny=ny, tau=tau, A_s=A_s, A_nci=N_c * sigma / h_min, h_min=h_min)
+    return Case(p, r1.ravel(), r2.ravel(), u.reshape(2, N),
+                {"type": T, "H": H, "h": h, "W_out": W_out, "u_d": u_d, "u_c": u_c, "phi": phi,
+                 "x_out0": xj + H + L_o, "junction": (xj, y0, y1)})
