@@ -87,7 +87,8 @@ def main(argv=None):
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp32_f32"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep", "unet", "analysis"])
+    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep", "unet", "analysis", "geometry",
+                                                          "focuser"])
     ap.add_argument("--batch", type=int, default=16, help="U-Net training batch (--workload unet)")
     ap.add_argument("--mode", default="persistent", choices=["persistent", "launch"])
     a = ap.parse_args(argv)
@@ -107,6 +108,10 @@ def main(argv=None):
         return bench_unet(a)
     if a.workload == "analysis":
         return bench_analysis(a)
+    if a.workload == "geometry":
+        return bench_geometry(a)
+    if a.workload == "focuser":
+        return bench_focuser(a)
     case = synth.hex_channel_3d()
     prm = case.params
     dim = 3
@@ -231,6 +236,68 @@ def bench_unet(a):
                       "batch": B, "params": net.n_params, "gflop_per_sample_fwd": round(fwd / B / 1e9, 3)},
            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
                         "frac": round(tflops / 2500.0, 4), "traffic": None}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_geometry(a):
+    """The 3-D benchmark channel with its wall rows given as solid nodes of a
+    node-type geometry (lb_set_geometry): the GEOM kernels on the benchmark
+    workload, to set their cost beside the built-in walls."""
+    import numpy as np
+    import synth
+    import paper_2003_11069_amd as P
+    case = synth.hex_channel_3d()
+    prm = dict(case.params, walls_y=0)
+    nx, ny, nz = prm["nx"], prm["ny"], prm["nz"]
+    t = np.zeros((nz, ny, nx), np.uint8)
+    t[:, 0] = t[:, -1] = 1
+    fluid = nx * (ny - 2) * nz
+    L = P.Lattice(P.Params.from_dict(prm, storage=P.STORAGE[a.storage]))
+    L.set_geometry(t.ravel(), case.rho1, case.rho2)
+    L.init_fields(case.rho1, case.rho2)
+    L.step(a.warmup)
+    L.kernel_times()
+    t0 = time.perf_counter()
+    L.step(a.steps)
+    L.kernel_times()
+    el = time.perf_counter() - t0
+    L.profile(True)
+    L.step(min(a.steps, 500))
+    kt = L.kernel_times()
+    L.profile(False)
+    mlups = fluid * a.steps / el / 1e6
+    out = {"metric": "MLUPS with a node-type geometry", "value": round(mlups, 2), "unit": "MLUPS",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(el / a.steps * 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp32": "f64", "fp16": "f32", "bf16": "f32", "fp32_f32": "f32"}[a.storage],
+           "data": "synthetic (seeded droplet packing)",
+           "config": {"workload": "D3Q27 droplet channel 256x64x64, wall rows as solid nodes",
+                      "fluid_nodes": fluid, "storage": a.storage},
+           "step": {"k_phase_avg_ms": round(kt["ms_phase"] / max(kt["launches"], 1), 5),
+                    "k_main_avg_ms": round(kt["ms_main"] / max(kt["launches"], 1), 5), "graphs": L.graphs}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_focuser(a):
+    """Droplet generation in the 2-D flow-focuser (scale 2, phi 0.25):
+    lattice throughput of the geometry step and the generation frequency,
+    droplet volume and Q_d = nu V_d (see paper_2003_11069_amd.focuser)."""
+    from paper_2003_11069_amd import focuser
+    steps = max(a.steps, 40000)
+    r = focuser.run(steps=steps, t_skip=min(20000, steps // 3), storage=a.storage)
+    mlups = r["fluid_nodes"] * steps / r["seconds"] / 1e6
+    out = {"metric": "flow-focuser droplet generation", "value": round(mlups, 2), "unit": "MLUPS",
+           "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(r["seconds"] / steps * 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp32": "f64", "fp16": "f32", "bf16": "f32", "fp32_f32": "f32"}[a.storage],
+           "data": "synthetic (flow-focuser geometry, inlet speeds)",
+           "config": {"workload": f"D2Q9 flow-focuser {r['nx']}x{r['ny']}, phi {r['phi']}",
+                      "storage": a.storage},
+           "droplets": {k: r[k] for k in ("V_d", "nu", "Q_d", "droplets_crossed", "flux_xc_mean",
+                                          "inlet_dispersed_flux", "x_c")},
+           "note": "timed region includes the droplet sampling every 250 steps"}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -185,6 +185,37 @@ int lb_kernel_times(lb_handle *h, double *ms_phase, double *ms_main, int64_t *la
  * Allocates and frees two device buffers. */
 int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double *gbps);
 
+/* ---- Node-type geometry (Results: droplet generation in a flow-focuser,
+ * Fig. 1 -- a device with inlet channels, a striction and an outlet) --------
+ * lb_set_geometry turns the periodic lattice into a device: type[n] is one of
+ *   LB_NODE_FLUID  updated by the LB step;
+ *   LB_NODE_SOLID  half-way bounce-back for its fluid neighbours; its psi
+ *                  (for the colour gradient) is the w_i-weighted mean of the
+ *                  psi of its non-solid neighbours (neutral wetting), 0 if
+ *                  it has none; the NCI probe stops at it;
+ *   LB_NODE_INLET  velocity inlet: after every collision it holds the
+ *                  equilibrium at velocity u[n] and composition
+ *                  rho1[n]/(rho1[n] + rho2[n]) with the density of its
+ *                  feeder; psi = its composition;
+ *   LB_NODE_OUTLET pressure outlet: the equilibrium at density
+ *                  rho1[n] + rho2[n] with the velocity and composition of
+ *                  its feeder; psi = the feeder's.
+ * The feeder of an inlet/outlet node is its first fluid neighbour along -x,
+ * +x, -y, +y, -z, +z (one is required).  The NCI probe also stops at inlet and
+ * outlet nodes.  type, rho1, rho2 (N) and u (dim*N, may be NULL: zero inlet
+ * velocity) are host arrays read during the call.  Requires walls_y == 0
+ * (walls are solid nodes) and nci_mode == 0; call before lb_init_fields /
+ * lb_set_populations (which then initialise fluid nodes only), once per
+ * handle.  Errors: LB_EINVAL (bad type value, an inlet/outlet without a fluid
+ * axis neighbour, invalid prescribed densities, walls_y or nci_mode set, a
+ * second call), LB_ENOMEM, LB_EDEVICE.  Single lattices only (not batches). */
+#define LB_NODE_FLUID 0
+#define LB_NODE_SOLID 1
+#define LB_NODE_INLET 2
+#define LB_NODE_OUTLET 3
+int lb_set_geometry(lb_handle *h, const uint8_t *type, const double *rho1, const double *rho2,
+                    const double *u);
+
 /* ---- Droplet-level analysis (Results: droplet count and volume, the
  * hex-n arrangements named by their number of droplet rows, vorticity of the
  * flow) ----------------------------------------------------------------

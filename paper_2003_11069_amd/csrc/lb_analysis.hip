@@ -531,8 +531,15 @@ Geo geo_of(const lb_handle *h) {
 }
 
 // The FIELDS pass of the lattice kernels into the arena.  It writes every
-// fluid node; the analysis kernels never read wall rows.
+// fluid node; the analysis kernels never read wall rows, but with a node-type
+// geometry the other non-fluid nodes must read as zero (no phase, u = 0).
 int fields_to_arena(lb_handle *h, const Arena &a) {
+  if (h->geom) {
+    const size_t N = (size_t)h->N;
+    HIP_TRY(hipMemsetAsync(a.r1, 0, 8 * N, h->stream));
+    HIP_TRY(hipMemsetAsync(a.r2, 0, 8 * N, h->stream));
+    HIP_TRY(hipMemsetAsync(a.u, 0, 8 * (size_t)h->D * N, h->stream));
+  }
   return dispatch(h, FIELDS, a.r1, a.r2, a.u, nullptr);
 }
 

@@ -127,6 +127,7 @@ int run_pass(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t
 }
 
 int dispatch(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t *io) {
+  if (h->geom) return dispatch_geom(h, mode, o0, o1, o2, io);
   const bool d2 = h->D == 2;
   switch (h->store) {
     case LB_STORE_FP32:
@@ -192,6 +193,7 @@ int alloc(lb_handle *h, void **ptr, size_t bytes) {
 }
 
 bool is_wall(const lb_handle *h, int64_t n) {
+  if (h->geom) return h->type[(size_t)n] != LB_NODE_FLUID;
   if (!h->p.walls_y) return false;
   const int y = (int)((n / h->p.nx) % h->p.ny);
   return y == 0 || y == h->p.ny - 1;
@@ -291,6 +293,7 @@ void lb_destroy(lb_handle *h) {
   (void)hipFree(h->partials);
   (void)hipFree(h->obs);
   analysis_free(h);
+  geometry_free(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   for (int k = 0; k < 2; ++k)
     if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);

@@ -79,6 +79,15 @@ struct lb_handle {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int graphs_ok = 1;
+  // node-type geometry (lb_set_geometry): mask words, open-boundary and
+  // derived-psi lists on the device, the node types on the host
+  int geom = 0;
+  uint32_t *nbm = nullptr;
+  void *bc = nullptr;           // lbi::BCNode[n_bc]
+  int32_t *psi_out = nullptr;   // outlet node, feeder pairs
+  int32_t *psi_solid = nullptr; // solid nodes with a non-solid neighbour
+  int n_bc = 0, n_psi_out = 0, n_psi_solid = 0;
+  std::vector<uint8_t> type;
   // droplet analysis and vorticity: one device arena, allocated on first use
   void *ana = nullptr;
   size_t ana_bytes = 0;
@@ -100,6 +109,21 @@ int dispatch(lb_handle *h, int mode, double *o0 = nullptr, double *o1 = nullptr,
 int validate(const lb_params *p);
 // Releases the droplet-analysis arena and events of a handle.
 void analysis_free(lb_handle *h);
+// Grid sizes of the single-lattice kernels.
+int blocks_main(const lb_handle *h);
+int blocks_phase(const lb_handle *h);
+// Releases the geometry buffers of a handle.
+void geometry_free(lb_handle *h);
+// One pass of the geometry kernels (handles with lb_set_geometry).
+int dispatch_geom(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t *io);
+// Open-boundary node: inlet (velocity, composition prescribed) or outlet
+// (density prescribed), refreshed from its feeder after every collision.
+struct BCNode {
+  int32_t node, feeder, kind, pad;  // kind: LB_NODE_INLET or LB_NODE_OUTLET
+  double frac1;                     // inlet: rho1/rho; outlet: unused
+  double rho;                       // outlet: density; inlet: unused
+  double u[3];                      // inlet velocity
+};
 int reduce_obs(lb_handle *h, int record);
 // Kernel arguments of a handle reading state copy `in` and writing `out`.
 template <typename S, typename R>
@@ -127,6 +151,7 @@ inline lbk::Args<S, R> make_args(lb_handle *h, int in, int out) {
   a.r1 = (R *)h->r1;
   a.partials = h->partials;
   a.xcd_remap = h->xcd_remap;
+  a.nbm = h->nbm;
   return a;
 }
 }  // namespace lbi

@@ -120,7 +120,12 @@ struct Args {
   double *f_out0, *f_out1, *f_out2; // FIELDS/POPS/DIAG outputs
   int32_t *i_out;     // DIAG: hit distance
   int xcd_remap;      // 1: contiguous tile ranges per XCD
+  const uint32_t *nbm; // node-type geometry (GEOM kernels): bit i set when the
+                       // source x - c_i is solid; GEO_SOLID, GEO_NONFLUID flags
 };
+
+// Flags of the geometry mask word.
+constexpr uint32_t GEO_SOLID = 1u << 30, GEO_NONFLUID = 1u << 31;
 
 enum Mode { STEP = 0, STEP_OBS = 1, OBSERVE = 2, FIELDS = 3, POPS = 4, DIAG = 5 };
 enum Src { PULL = 0, EXPLICIT = 1 };
@@ -240,10 +245,10 @@ __device__ __forceinline__ uint32_t source(const Wrap &w, uint32_t n, int cx, in
 // source in a wall row means bounce-back, i.e. the node's own scalars with the
 // colour term's sign flipped (c_opp(i) = -c_i).
 template <int D, typename S, typename R, int SRC, int COL, bool WANT_C1, int PX = 1, int PY = 1,
-          int TS = 1>
+          int TS = 1, int GEOM = 0>
 __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, uint32_t n,
                                      const R *ta, const float *tB, int lidx, float *f, R *c1out,
-                                     R &dr, R &r1, R *j) {
+                                     R &dr, R &r1, R *j, uint32_t gm = 0u) {
   using L = Lat<D>;
   constexpr uint32_t SB = sizeof(S);
   dr = 0; r1 = 0;
@@ -264,7 +269,8 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
       if (!is_fp32<S>::value && i == L::REST) sv = ld(A.in.s0, n);
       else sv = to_f(ldb(A.in.s, nb + of.x[cx + 1] + of.y[cy + 1] + of.z[cz + 1] + (uint32_t)i * NB));
       if (COL != COL_NONE) {
-        const bool bb = A.walls && cy != 0 && (y - cy == 0 || y - cy == A.ny - 1);
+        const bool bb = GEOM ? ((gm >> i) & 1u) != 0u
+                             : (A.walls && cy != 0 && (y - cy == 0 || y - cy == A.ny - 1));
         const R sgn = bb ? (R)-1 : (R)1;
         R av, Bx = 0, By = 0, Bz = 0;
         if (COL == COL_GLOBAL) {
@@ -309,7 +315,7 @@ struct PhaseTile {
   static constexpr int TS = PX * PY * PZ;
 };
 
-template <int D, typename S, typename R, int SRC, int TZP>
+template <int D, typename S, typename R, int SRC, int TZP, int GEOM = 0>
 __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, int bz, R *ta,
                                            float *tB) {
   constexpr int PX = PhaseTile<D, TZP>::PX, PY = PhaseTile<D, TZP>::PY;
@@ -337,10 +343,13 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
       const int z = z0 + tz;
       if (z >= A.nz) break;
       const uint32_t n = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
+      const uint32_t gm = GEOM ? ld(A.nbm, n) : 0u;
+      if (GEOM && (gm & GEO_NONFLUID)) continue;
       const int lidx = (threadIdx.x + 1) + PX * ((threadIdx.y + 1) + PY * ((D == 3) ? tz + 1 : 0));
       float f[Lat<D>::Q];
       R dr, r1, j[3];
-      pull<D, S, R, SRC, COL_LDS, false, PX, PY, TS>(A, x, y, z, n, ta, tB, lidx, f, nullptr, dr, r1, j);
+      pull<D, S, R, SRC, COL_LDS, false, PX, PY, TS, GEOM>(A, x, y, z, n, ta, tB, lidx, f, nullptr, dr, r1,
+                                                           j, gm);
       const R rho = (R)1 + dr;
       st(A.psi, n, ((R)2 * r1 - rho) / rho);
       st(A.r1, n, r1);
@@ -363,7 +372,7 @@ __device__ __forceinline__ void phase_decode(int nx, int ny, int lb, int &bx, in
 }
 
 // k_phase: one phase tile per block over a single lattice.
-template <int D, typename S, typename R, int SRC, int TZP, int WPE = 1>
+template <int D, typename S, typename R, int SRC, int TZP, int WPE = 1, int GEOM = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_phase(Args<S, R> A) {
   constexpr int TS = PhaseTile<D, TZP>::TS;
   constexpr bool STAGE = (SRC == PULL);
@@ -371,7 +380,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   __shared__ float tB[STAGE ? D * TS : 1];
   int bx, by, bz;
   phase_decode<D, TZP>(A.nx, A.ny, logical_block(blockIdx.x, gridDim.x, A.xcd_remap), bx, by, bz);
-  phase_tile<D, S, R, SRC, TZP>(A, bx, by, bz, ta, tB);
+  phase_tile<D, S, R, SRC, TZP, GEOM>(A, bx, by, bz, ta, tB);
 }
 
 // A_h: A below h_min, A (h_min/h)^3 up to h_max, 0 beyond (Eq. near_c text).
@@ -426,7 +435,8 @@ __device__ __forceinline__ void main_decode(int nx, int ny, int lb, int &bx, int
   bz = lb / (gx * gy);
 }
 
-template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int NCI = 0>
+template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int NCI = 0,
+          int GEOM = 0>
 __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, int bz, int slot,
                                           R *tile, double (*red)[8]) {
   using L = Lat<D>;
@@ -458,6 +468,8 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
     const int z = z0 + tz;
     if (!xy_ok || z >= A.nz) continue;
     const uint32_t n = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
+    const uint32_t gm = GEOM ? ld(A.nbm, n) : 0u;
+    if (GEOM && (gm & GEO_NONFLUID)) continue;
     const int lx = threadIdx.x + H, ly = threadIdx.y + H, lz = (D == 3) ? tz + H : 0;
     auto T = [&](int ox, int oy, int oz) -> R {
       return tile[(lx + ox) + LX * ((ly + oy) + LY * (lz + oz))];
@@ -537,8 +549,24 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         const int oz = (D == 3) ? (int)round_away((R)s * nn[2]) : 0;
         const int yt = y + oy;
         if (A.walls && (yt <= 0 || yt >= A.ny - 1)) break;
+        if (GEOM) {  // the probe stops at any node that is not fluid
+          const uint32_t ns = (uint32_t)wrapi(x + ox, A.nx) +
+                              (uint32_t)A.nx * ((uint32_t)wrapi(yt, A.ny) +
+                                                (uint32_t)A.ny * ((D == 3) ? wrapi(z + oz, A.nz) : 0));
+          if (ld(A.nbm, ns) & GEO_NONFLUID) break;
+        }
         R pv;
-        if (abs(ox) <= H && abs(oy) <= H && abs(oz) <= H) {
+        if constexpr (GEOM) {
+          // LDS value read at clamped offsets, the global value only beyond
+          // the halo (keeps the two loads apart)
+          const bool inside = abs(ox) <= H && abs(oy) <= H && abs(oz) <= H;
+          pv = T(min(max(ox, -H), H), min(max(oy, -H), H), min(max(oz, -H), H));
+          if (!inside) {
+            const int xt = wrapi(x + ox, A.nx);
+            const int zt = (D == 3) ? wrapi(z + oz, A.nz) : 0;
+            pv = ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)wrapi(yt, A.ny) + (uint32_t)A.ny * zt));
+          }
+        } else if (abs(ox) <= H && abs(oy) <= H && abs(oz) <= H) {
           pv = T(ox, oy, oz);
         } else {
           const int xt = wrapi(x + ox, A.nx);
@@ -570,9 +598,11 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
     float f[Q];
     R c1[Q], dr, r1, j[3];
     if (MODE == POPS)
-      pull<D, S, R, SRC, COL_GLOBAL, true>(A, x, y, z, n, nullptr, nullptr, 0, f, c1, dr, r1, j);
+      pull<D, S, R, SRC, COL_GLOBAL, true, 1, 1, 1, GEOM>(A, x, y, z, n, nullptr, nullptr, 0, f, c1, dr, r1,
+                                                          j, gm);
     else
-      pull<D, S, R, SRC, COL_NONE, false>(A, x, y, z, n, nullptr, nullptr, 0, f, c1, dr, r1, j);
+      pull<D, S, R, SRC, COL_NONE, false, 1, 1, 1, GEOM>(A, x, y, z, n, nullptr, nullptr, 0, f, c1, dr, r1,
+                                                         j, gm);
     r1 = ld(A.r1, n);
     const R rho = (R)1 + dr;
 
@@ -666,8 +696,21 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
               (uint32_t)xw + (uint32_t)A.nx * ((uint32_t)(y + dcy) + (uint32_t)A.ny * zw);
           stb_out<1>(A.out.s, nw * (uint32_t)sizeof(S) + (uint32_t)L::opp(d) * NB, q);
         };
-        if ((icy == -1 && low) || (icy == 1 && high)) ghost(i, icx, icy, icz, q_i);
-        if ((icy == 1 && low) || (icy == -1 && high)) ghost(io, -icx, -icy, -icz, q_o);
+        if constexpr (GEOM) {
+          // populations heading into a solid node x + c_d: reflected copy in
+          // its slot opp(d) (bit k of gm: the source x - c_k is solid)
+          auto ghost_g = [&](int d, int dcx, int dcy, int dcz, S q) {
+            const uint32_t nw = (uint32_t)wrapi(x + dcx, A.nx) +
+                                (uint32_t)A.nx * ((uint32_t)wrapi(y + dcy, A.ny) +
+                                                  (uint32_t)A.ny * ((D == 3) ? wrapi(z + dcz, A.nz) : 0));
+            stb_out<1>(A.out.s, nw * (uint32_t)sizeof(S) + (uint32_t)L::opp(d) * NB, q);
+          };
+          if ((gm >> io) & 1u) ghost_g(i, icx, icy, icz, q_i);
+          if ((gm >> i) & 1u) ghost_g(io, -icx, -icy, -icz, q_o);
+        } else {
+          if ((icy == -1 && low) || (icy == 1 && high)) ghost(i, icx, icy, icz, q_i);
+          if ((icy == 1 && low) || (icy == -1 && high)) ghost(io, -icx, -icy, -icz, q_o);
+        }
         sum_q += (R)L::w(i) * ((R)to_f(q_i) + (R)to_f(q_o));
       }
       const float srest = (float)((dr - sum_q) * (R)(1.0 / L::w(L::REST)));
@@ -707,13 +750,14 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
 
 // k_main: one main tile per block over a single lattice (NCI: 0 the integer
 // probe, 1 the continuous-NCI variant).
-template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int WPE = 1, int NCI = 0>
+template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int WPE = 1, int NCI = 0,
+          int GEOM = 0>
 __global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void k_main(Args<S, R> A) {
   __shared__ R tile[MainTile<D, BY, TZ, H>::TS];
   __shared__ double red[BY][8];
   int bx, by, bz;
   main_decode<D, BY>(A.nx, A.ny, logical_block(blockIdx.x, gridDim.x, A.xcd_remap), bx, by, bz);
-  main_tile<D, S, R, SRC, MODE, BY, TZ, H, NCI>(A, bx, by, bz, blockIdx.x, tile, red);
+  main_tile<D, S, R, SRC, MODE, BY, TZ, H, NCI, GEOM>(A, bx, by, bz, blockIdx.x, tile, red);
 }
 
 

@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "lb_droplets": ([vp, P(lb_droplet_stats), ip, C.c_int64, P(C.c_int64), P(C.c_int64), dp],
                         C.c_int),
         "lb_vorticity": ([vp, dp], C.c_int),
+        "lb_set_geometry": ([vp, C.POINTER(C.c_uint8), dp, dp, dp], C.c_int),
         "lb_analysis_times": ([vp, dp, dp], C.c_int),
         "lb_batch_create": ([P(lb_params), C.c_int32, vp, P(vp)], C.c_int),
         "lb_batch_init_fields": ([vp, C.c_int32, dp, dp, dp], C.c_int),
@@ -231,6 +232,20 @@ class Lattice:
     @property
     def device_bytes(self) -> int:
         return self.lib.lb_device_bytes(self.h)
+
+    def set_geometry(self, node_type, rho1, rho2, u=None):
+        """lb_set_geometry: node types (LB_NODE_*), and the inlet/outlet
+        prescriptions carried in rho1, rho2, u at those nodes."""
+        t = np.ascontiguousarray(node_type, np.uint8).ravel()
+        r1 = np.ascontiguousarray(rho1, np.float64).ravel()
+        r2 = np.ascontiguousarray(rho2, np.float64).ravel()
+        uu = None if u is None else np.ascontiguousarray(u, np.float64).ravel()
+        if t.size != self.N or r1.size != self.N or r2.size != self.N:
+            raise ValueError("geometry arrays must have N entries")
+        if uu is not None and uu.size != self.p.dim * self.N:
+            raise ValueError("u must have dim*N entries")
+        _check(self.lib.lb_set_geometry(self.h, t.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(r1), _dp(r2),
+                                        _dp(uu)))
 
     def init_fields(self, rho1, rho2, u=None):
         r1 = np.ascontiguousarray(rho1, np.float64).ravel()

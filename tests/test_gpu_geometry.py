@@ -1,0 +1,133 @@
+"""GPU parity of the node-type geometry (lb_set_geometry: solid nodes,
+velocity inlets, pressure outlets) against the FP64 oracle running the same
+geometry: closed boxes with obstacles (2-D and 3-D, NCI active), a
+pressure-driven channel between an inlet and an outlet, the flow-focuser of
+the paper's Fig. 1 in FP32 and FP16 storage; the mask form of the wall rows
+against the built-in walls; mass conservation; droplet analysis on a device;
+invalid geometries."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import analysis as An
+import paper_2003_11069_amd as P
+from gpu_common import say, fluid_mask, field_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _pair(case, storage="fp32", **over):
+    d = dict(case.params)
+    d.update(over)
+    o = oracle.Oracle(oracle.Params(**{k: v for k, v in d.items() if k in oracle.Params.__dataclass_fields__}))
+    o.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
+    o.init_fields(case.rho1, case.rho2, case.u)
+    g = P.Lattice(P.Params.from_dict(d, storage=P.STORAGE[storage]))
+    g.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
+    g.init_fields(case.rho1, case.rho2, case.u)
+    return o, g
+
+
+CASES = {
+    "obstacle_box_2d": lambda: synth.obstacle_box(nx=70, ny=45),
+    "obstacle_box_3d": lambda: synth.obstacle_box(nx=37, ny=30, lattice=1, nz=9),
+    "inlet_outlet_channel": lambda: synth.inlet_outlet_channel(nx=90, ny=30, u_in=0.02),
+    "flow_focuser": lambda: synth.flow_focuser_2d(),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_free_run_parity(name):
+    case = CASES[name]()
+    steps = 400 if name == "flow_focuser" else 200
+    say(f"[gpu] geometry {name}, {steps} steps")
+    o, g = _pair(case)
+    o.step(steps)
+    g.step(steps)
+    mask = case.info["type"] == synth.FLUID
+    e = field_errors(o, g, mask)
+    say(f"  errors {e}")
+    assert e["rho1"] <= TOL and e["rho2"] <= TOL and e["u"] <= TOL
+    # non-fluid nodes report zero fields
+    r1, r2, u = g.fields()
+    assert np.all(r1[~mask] == 0) and np.all(u[:, ~mask] == 0)
+
+
+def test_flow_focuser_fp16_within_budget():
+    case = synth.flow_focuser_2d()
+    say("[gpu] flow-focuser, FP16 storage, 400 steps")
+    o, g = _pair(case, storage="fp16")
+    o.step(400)
+    g.step(400)
+    e = field_errors(o, g, case.info["type"] == synth.FLUID)
+    say(f"  errors {e}")
+    assert e["rho1"] <= 2e-3 and e["rho2"] <= 2e-3 and e["u"] <= 0.2
+
+
+def test_mask_walls_equal_builtin_walls():
+    case = synth.solid_wall_channel(nx=100, ny=34, force=1e-5)
+    say("[gpu] solid rows vs built-in walls, single phase, 300 steps")
+    g = P.Lattice(P.Params.from_dict(case.params))
+    g.set_geometry(case.info["type"], case.rho1, case.rho2)
+    g.init_fields(case.rho1, case.rho2)
+    w = P.Lattice(P.Params.from_dict({**case.params, "walls_y": 1}))
+    w.init_fields(case.rho1, case.rho2)
+    g.step(300)
+    w.step(300)
+    fluid = case.info["type"] == synth.FLUID
+    for a, b in zip(g.fields(), w.fields()):
+        a = np.asarray(a).reshape(-1, case.N)[:, fluid]
+        b = np.asarray(b).reshape(-1, case.N)[:, fluid]
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-14)
+
+
+def test_closed_box_mass_conservation():
+    case = synth.obstacle_box(nx=128, ny=64)
+    say("[gpu] closed box with obstacles, 2000 steps, component masses")
+    g = P.Lattice(P.Params.from_dict(case.params))
+    g.set_geometry(case.info["type"], case.rho1, case.rho2)
+    g.init_fields(case.rho1, case.rho2)
+    m0 = g.observables()["mass"]
+    g.step(2000)
+    m1 = g.observables()["mass"]
+    say(f"  relative drift {(m1 - m0) / m0}")
+    assert np.all(np.abs((m1 - m0) / m0) <= 1e-9)
+
+
+def test_droplet_analysis_on_a_device():
+    case = synth.flow_focuser_2d()
+    say("[gpu] droplet analysis and vorticity on the flow-focuser after 300 steps")
+    g = P.Lattice(P.Params.from_dict(case.params))
+    g.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
+    g.init_fields(case.rho1, case.rho2, case.u)
+    g.step(300)
+    p = case.params
+    r1, r2, u = g.fields()
+    d = g.droplets()
+    m = An.dispersed_mask(r1, r2, p["nx"], p["ny"], 1, 0)
+    lab, n = An.components(m, (True, True, True))
+    assert d["count"] == n and np.array_equal(d["labels"], lab.ravel().astype(np.int32))
+    assert np.array_equal(g.vorticity(), An.vorticity(u, p["nx"], p["ny"], 1, 0))
+
+
+def test_invalid_geometries_are_rejected():
+    case = synth.inlet_outlet_channel(nx=20, ny=10)
+    g = P.Lattice(P.Params.from_dict({**case.params, "walls_y": 1}))
+    with pytest.raises(P.LBError):
+        g.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
+    g = P.Lattice(P.Params.from_dict(case.params))
+    t = case.info["type"].reshape(10, 20).copy()
+    t[3:6, 7:10] = synth.SOLID
+    t[4, 8] = synth.INLET
+    with pytest.raises(P.LBError):
+        g.set_geometry(t.ravel(), case.rho1, case.rho2, case.u)
+    bad = case.info["type"].copy()
+    bad[0] = 7
+    with pytest.raises(P.LBError):
+        g.set_geometry(bad, case.rho1, case.rho2, case.u)
+    g.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
+    with pytest.raises(P.LBError):  # once per handle
+        g.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
