@@ -82,35 +82,27 @@ __global__ __launch_bounds__(256) void k_open_bc(Args<S, R> A, const BCNode *bc,
     j[2] += (R)L::cz(i) * wv;
   }
   const R rho = (R)1 + dr;
-  const R rho1 = ld(A.out.a, f) * rho;
-  R rb, r1b, u[3];
+  // composition: the inlet's prescribed fraction, or the feeder's own a, kept
+  // exactly (a pure phase stays pure)
+  R rb, frac, u[3];
   if (b.kind == LB_NODE_INLET) {
     rb = rho;
-    r1b = rho * (R)b.frac1;
+    frac = (R)b.frac1;
     for (int d = 0; d < 3; ++d) u[d] = (R)b.u[d];
   } else {
     rb = (R)b.rho;
-    r1b = rb * (rho1 / rho);
+    frac = ld(A.out.a, f);
     for (int d = 0; d < 3; ++d) u[d] = j[d] / rho;
   }
   const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  R sum = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const R cu = (R)L::cx(i) * u[0] + (R)L::cy(i) * u[1] + (R)L::cz(i) * u[2];
     const float sv = (float)((rb - (R)1) + rb * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
-    float stored;
-    if (!is_fp32<S>::value && i == L::REST) {
-      st(A.out.s0, node, sv);
-      stored = sv;
-    } else {
-      const S q = from_f<S>(sv);
-      A.out.s[(size_t)i * A.N + node] = q;
-      stored = to_f(q);
-    }
-    sum += (R)L::w(i) * (R)stored;
+    if (!is_fp32<S>::value && i == L::REST) st(A.out.s0, node, sv);
+    else A.out.s[(size_t)i * A.N + node] = from_f<S>(sv);
   }
-  st(A.out.a, node, r1b / ((R)1 + sum));
+  st(A.out.a, node, frac);
   for (int d = 0; d < D; ++d) st(A.out.B + (size_t)d * A.N, node, 0.0f);
 }
 
