@@ -23,6 +23,12 @@ definitions used here:
   Results): droplets of at least a quarter of the mean volume, sorted by
   centroid y; a gap in y larger than half the equivalent diameter of the
   median droplet starts a new row;
+* droplet generation (a device with an outlet channel): from droplet tables
+  sampled at a fixed interval, the main droplets are those of at least half
+  the 90th-percentile volume and V_d is their median volume; nu counts the
+  main droplets whose centroid passed the line x_c since the previous sample
+  (the droplet being the nearest earlier centroid at most one node ahead, 20
+  behind and 10 rows away), per step; Q_d = nu V_d (Results, Fig. 3);
 * vorticity: omega = curl u by central differences over the node grid
   (periodic wrap in the periodic directions; wall rows hold u = 0).
 
@@ -144,6 +150,28 @@ def rows(centroid_y, volumes, dim):
     vm = float(np.median(v[keep]))
     d_eq = 2.0 * (math.sqrt(vm / math.pi) if dim == 2 else (3.0 * vm / (4.0 * math.pi)) ** (1.0 / 3.0))
     return 1 + int(np.count_nonzero(np.diff(y) > 0.5 * d_eq))
+
+
+def generation_stats(samples, xc):
+    """(V_d, crossings, nu) from samples [(t, centroids [k, 2] as (x, y),
+    volumes [k])] of the droplets downstream of a striction."""
+    vols = [np.asarray(v, np.float64) for _, _, v in samples]
+    allv = np.concatenate(vols) if vols else np.zeros(0)
+    V_d = float(np.median(allv[allv >= 0.5 * np.percentile(allv, 90)])) if allv.size else 0.0
+    n = 0
+    for k in range(1, len(samples)):
+        prev_c = np.asarray(samples[k - 1][1], np.float64)
+        for (x, y), v in zip(np.asarray(samples[k][1], np.float64), samples[k][2]):
+            if v < 0.5 * V_d or x < xc or prev_c.size == 0:
+                continue
+            near = (prev_c[:, 0] <= x + 1) & (prev_c[:, 0] > x - 20) & (np.abs(prev_c[:, 1] - y) < 10)
+            if not near.any():
+                continue
+            cand = prev_c[near]
+            j = int(np.argmin((cand[:, 0] - x) ** 2 + (cand[:, 1] - y) ** 2))
+            n += int(cand[j, 0] < xc)
+    span = samples[-1][0] - samples[0][0] if len(samples) > 1 else 1
+    return V_d, n, n / span
 
 
 def vorticity(u, nx, ny, nz, walls_y):

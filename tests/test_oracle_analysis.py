@@ -185,3 +185,25 @@ def test_rows_of_synthetic_channels(seed, n_rows):
     assert n == c.info["n_droplets"]
     roots, vols, cen = A.droplet_table(lab, p["nx"], p["ny"], 1, 1)
     assert A.rows(cen[:, 1], vols, 2) == n_rows
+
+
+@pytest.mark.parametrize("period,speed", [(6600, 0.007), (2500, 0.015)])
+def test_generation_stats_of_a_droplet_train(period, speed):
+    """Main droplets born every `period` steps at the striction and moving at
+    `speed`, each with a trailing satellite: nu = 1/period, V_d = the main
+    volume."""
+    rng = np.random.default_rng(3)
+    x0, xc, L = 113, 190, 430
+    samples = []
+    for t in range(0, 150000, 250):
+        births = np.arange(0, t + 1, period)
+        x = x0 + 4 + speed * (t - births)
+        x = x[x < L]
+        y = 48.0 + rng.uniform(-1, 1, x.size)
+        cen = np.concatenate([np.stack([x, y], 1), np.stack([x - 12, y], 1)])
+        vol = np.concatenate([400 + rng.integers(-5, 6, x.size), np.full(x.size, 50)])
+        keep = cen[:, 0] > x0
+        samples.append((t, cen[keep], vol[keep]))
+    V_d, n, nu = A.generation_stats(samples, xc)
+    assert V_d == pytest.approx(400, abs=5)
+    assert nu == pytest.approx(1 / period, rel=0.05)
