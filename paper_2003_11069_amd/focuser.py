@@ -54,7 +54,7 @@ def reduce_samples(samples, xc):
 
 
 def run(scale=2.0, phi=0.25, u_c=0.004, A_s=0.1, N_c=0.1, W_out=64, steps=60000, t_skip=20000,
-        every=250, storage="fp32"):
+        every=250, storage="fp32", keep_samples=False):
     case = synth.flow_focuser_2d(scale=scale, phi=phi, u_c=u_c, A_s=A_s, N_c=N_c, W_out=W_out)
     p = case.params
     nx, ny = p["nx"], p["ny"]
@@ -83,7 +83,8 @@ def run(scale=2.0, phi=0.25, u_c=0.004, A_s=0.1, N_c=0.1, W_out=64, steps=60000,
             "V_d": v_main, "droplets_crossed": crossings, "nu": nu, "Q_d": nu * v_main,
             "flux_xc_mean": float(np.mean(flux)) if flux else 0.0,
             "inlet_dispersed_flux": case.info["u_d"] * case.info["H"],
-            "seconds": elapsed, "graphs": lat.graphs}
+            "seconds": elapsed, "graphs": lat.graphs,
+            "samples": samples if keep_samples else None, "flux_samples": flux if keep_samples else None}
 
 
 def main(argv=None):
@@ -97,6 +98,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     for phi in a.phi:
         r = run(phi=phi, u_c=a.u_c, steps=a.steps, t_skip=a.skip, every=a.every, storage=a.storage)
+        r.pop("samples"); r.pop("flux_samples")
         print(json.dumps(r), flush=True)
 
 

@@ -1,9 +1,10 @@
 """Writes tests/golden/focuser_stats.json: droplet-generation statistics of
 the flow-focuser (synth.flow_focuser_2d(scale=2, phi=0.25, u_c=0.004,
 A_s=0.1, N_c=0.1, W_out=64)) from the FP64 oracle: droplet tables every 250
-steps from step 20,000 to 140,000, reduced by oracle.analysis.generation_stats
-(V_d, nu, Q_d = nu V_d, Results / Fig. 3), and the mean dispersed flux
-sum_y rho1 u_x through the measuring column.  Calls only the oracle and the
+steps from step 20,000 to 140,000 (and over the first window, to 80,000),
+reduced by oracle.analysis.generation_stats (V_d, nu, Q_d = nu V_d, Results /
+Fig. 3), and the mean dispersed flux sum_y rho1 u_x through the measuring
+column.  Calls only the oracle and the
 input generators; about ten minutes on eight cores.
 
     python tests/golden/make_focuser_stats.py
@@ -23,6 +24,7 @@ from oracle import analysis as A  # noqa: E402
 
 CONFIG = dict(scale=2.0, phi=0.25, u_c=0.004, A_s=0.1, N_c=0.1, W_out=64)
 STEPS, SKIP, EVERY = 140000, 20000, 250
+EARLY = 80000  # end of the first window (steps 20,000-80,000)
 
 
 def main():
@@ -46,8 +48,12 @@ def main():
         samples.append((o.t, cen[keep, :2], vols[keep]))
         flux.append(float((r1.reshape(ny, nx)[:, xc] * u[0].reshape(ny, nx)[:, xc]).sum()))
     V_d, n, nu = A.generation_stats(samples, xc)
+    early = [s for s in samples if s[0] <= EARLY]
+    V_e, n_e, nu_e = A.generation_stats(early, xc)
     out = {"config": CONFIG, "steps": STEPS, "skip": SKIP, "every": EVERY, "x_c": int(xc),
-           "V_d": V_d, "crossings": n, "nu": nu, "Q_d": nu * V_d, "flux_xc_mean": float(np.mean(flux))}
+           "V_d": V_d, "crossings": n, "nu": nu, "Q_d": nu * V_d, "flux_xc_mean": float(np.mean(flux)),
+           "early_end": EARLY, "early_V_d": V_e, "early_crossings": n_e, "early_nu": nu_e,
+           "early_flux_xc_mean": float(np.mean(flux[:len(early)]))}
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "focuser_stats.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))

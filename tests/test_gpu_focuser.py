@@ -1,11 +1,13 @@
 """Flow-focuser droplet generation on the GPU against the FP64 oracle's
 statistics (tests/golden/focuser_stats.json, written by
-tests/golden/make_focuser_stats.py from the oracle): over steps
-20,000-140,000 the number of main droplets crossing the measuring line, their
-median volume V_d, nu and Q_d = nu V_d (Results, Fig. 3), and the mean
-dispersed flux through that line.  The flow is laminar and the generation
-periodic, so the statistics agree closely although the FP32 and FP64
-trajectories are not identical."""
+tests/golden/make_focuser_stats.py from the oracle).  Over steps
+20,000-80,000 the two runs generate the same droplets: the crossing count of
+the measuring line within one and V_d within 3 %.  Later the FP32 and FP64
+trajectories part (satellite droplets merge into main droplets at different
+moments, which trades count against volume), so over steps 20,000-140,000 the
+comparison is of what the inflow fixes: Q_d = nu V_d within 3 % and the
+dispersed flux through the line within 1 %, with nu and V_d only required to
+stay in the same regime (within 25 %)."""
 import json
 import os
 
@@ -24,12 +26,19 @@ def test_generation_statistics_match_the_oracle():
     cfg = ref["config"]
     say("[gpu] flow-focuser 433x98, 140k steps, droplet generation statistics")
     r = focuser.run(scale=cfg["scale"], phi=cfg["phi"], u_c=cfg["u_c"], A_s=cfg["A_s"], N_c=cfg["N_c"],
-                    W_out=cfg["W_out"], steps=ref["steps"], t_skip=ref["skip"], every=ref["every"])
-    say(f"  gpu: crossings {r['droplets_crossed']} V_d {r['V_d']} nu {r['nu']:.4e} Q_d {r['Q_d']:.4e} "
-        f"flux {r['flux_xc_mean']:.5f}; oracle: {ref['crossings']} {ref['V_d']} {ref['nu']:.4e} "
-        f"{ref['Q_d']:.4e} {ref['flux_xc_mean']:.5f}; {r['seconds']:.1f} s")
+                    W_out=cfg["W_out"], steps=ref["steps"], t_skip=ref["skip"], every=ref["every"],
+                    keep_samples=True)
+    early = [s for s in r["samples"] if s[0] <= ref["early_end"]]
+    V_e, n_e, nu_e = focuser.reduce_samples(early, r["x_c"])
+    say(f"  steps 20k-{ref['early_end'] // 1000}k: gpu crossings {n_e} V_d {V_e}; oracle "
+        f"{ref['early_crossings']} {ref['early_V_d']}")
+    say(f"  steps 20k-{ref['steps'] // 1000}k: gpu crossings {r['droplets_crossed']} V_d {r['V_d']} "
+        f"nu {r['nu']:.4e} Q_d {r['Q_d']:.4e} flux {r['flux_xc_mean']:.5f}; oracle {ref['crossings']} "
+        f"{ref['V_d']} {ref['nu']:.4e} {ref['Q_d']:.4e} {ref['flux_xc_mean']:.5f}; {r['seconds']:.1f} s")
     assert r["x_c"] == ref["x_c"]
-    assert abs(r["droplets_crossed"] - ref["crossings"]) <= 1
-    assert r["V_d"] == pytest.approx(ref["V_d"], rel=0.05)
-    assert r["Q_d"] == pytest.approx(ref["Q_d"], rel=0.1)
+    assert abs(n_e - ref["early_crossings"]) <= 1
+    assert V_e == pytest.approx(ref["early_V_d"], rel=0.03)
+    assert r["Q_d"] == pytest.approx(ref["Q_d"], rel=0.03)
     assert r["flux_xc_mean"] == pytest.approx(ref["flux_xc_mean"], rel=0.01)
+    assert r["nu"] == pytest.approx(ref["nu"], rel=0.25)
+    assert r["V_d"] == pytest.approx(ref["V_d"], rel=0.25)
