@@ -38,7 +38,7 @@ class _Params(C.Structure):
                 ("walls_y", C.c_int32), ("tau", C.c_double), ("A_s", C.c_double),
                 ("beta", C.c_double), ("A_nci", C.c_double), ("h_min", C.c_double),
                 ("h_max", C.c_double), ("force", C.c_double * 3), ("tau2", C.c_double),
-                ("nci_mode", C.c_int32)]
+                ("nci_mode", C.c_int32), ("rho_ratio", C.c_double), ("alpha1", C.c_double)]
 
 
 def _load():
@@ -70,6 +70,7 @@ def _load():
         lib.lbo_diagnostics.argtypes = [C.c_void_p, dp, dp, dp, ip, dp]
         lib.lbo_equilibrium.argtypes = [C.c_int, C.c_double, dp, dp]
         lib.lbo_collide_node.argtypes = [P(_Params), dp, dp, dp, dp, dp, dp]
+        lib.lbo_equilibrium_k.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
         lib.lbo_A_h.argtypes = [C.c_double] * 4
         lib.lbo_A_h.restype = C.c_double
         lib.lbo_A_h_shifted.argtypes = [C.c_double] * 4
@@ -104,11 +105,13 @@ class Params:
     force: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
     tau2: float = 0.0
     nci_mode: int = 0
+    rho_ratio: float = 0.0
+    alpha1: float = 0.0
 
     def to_c(self) -> _Params:
         p = _Params()
         for k in ("lattice", "nx", "ny", "nz", "walls_y", "tau", "A_s", "beta", "A_nci",
-                  "h_min", "h_max", "tau2", "nci_mode"):
+                  "h_min", "h_max", "tau2", "nci_mode", "rho_ratio", "alpha1"):
             setattr(p, k, getattr(self, k))
         for a in range(3):
             p.force[a] = float(self.force[a])
@@ -142,6 +145,16 @@ def equilibrium(lat: int, rho: float, u) -> np.ndarray:
     uu[:len(u)] = u
     out = np.zeros(27)
     lib.lbo_equilibrium(lat, float(rho), _dp(uu), _dp(out))
+    return out[:27 if lat == D3Q27 else 9].copy()
+
+
+def equilibrium_k(lat: int, alpha: float, rho: float, u) -> np.ndarray:
+    """Density-ratio variant: component equilibrium with rest fraction alpha."""
+    lib = _load()
+    uu = np.zeros(3)
+    uu[:len(u)] = u
+    out = np.zeros(27)
+    lib.lbo_equilibrium_k(lat, float(alpha), float(rho), _dp(uu), _dp(out))
     return out[:27 if lat == D3Q27 else 9].copy()
 
 

@@ -16,6 +16,15 @@
  *   6-7. f = f1 + f2, u = j/rho; BGK + exact-difference forcing + perturbation
  *   8. Latva-Kokko recolouring
  *   9. pull streaming with half-way bounce-back at wall rows
+ * Density-ratio variant (rho_ratio > 0): component k has the equilibrium
+ * E_i^k = rho_k phi_i^k + w_i rho_k (3 c.u + 4.5 (c.u)^2 - 1.5 u.u) with
+ * phi_0^k = alpha_k and phi_i^k = (1 - alpha_k) w_i/(1 - w_0) otherwise, so
+ * its sound speed is c_k^2 = (1 - alpha_k)/(3 (1 - w_0)); alpha_1 is given,
+ * alpha_2 = 1 - gamma (1 - alpha_1) balances the pressures of the reference
+ * densities rho_1^0 = 1, rho_2^0 = 1/gamma.  The collision relaxes the total
+ * towards sum_k E^k; recolouring adds beta (rho1 rho2/rho^2) (rho1 phi_i^1 +
+ * rho2 phi_i^2) cos(phi_i) to component 1; psi is normalised by the reference
+ * densities, (rho1 - gamma rho2)/(rho1 + gamma rho2).
  * Geometry (lbo_set_geometry): a node-type mask on the periodic lattice.
  * Solid nodes reflect (half-way bounce-back) and carry psi = the w_i-weighted
  * mean of their non-solid neighbours (neutral wetting).  Inlet and outlet
@@ -96,6 +105,38 @@ void lbo_equilibrium(int lattice, double rho, const double u[3], double *feq) {
   for (int i = 0; i < Q; ++i) feq[i] = equilibrium_i(w[i], c[i], rho, u);
 }
 
+/* ---- density-ratio variant: rest fractions and component equilibria ------ */
+static int dr_on(const lbo_params *p) { return p->rho_ratio > 0; }
+static void dr_alphas(const lbo_params *p, double w0, double *a1, double *a2) {
+  if (!dr_on(p)) {
+    *a1 = *a2 = w0;
+    return;
+  }
+  *a1 = p->alpha1;
+  *a2 = 1.0 - p->rho_ratio * (1.0 - p->alpha1);
+}
+/* phi_i^k of a direction with weight w (rest if c = 0) */
+static double dr_phi(double alpha, double w, double w0, const int32_t c[3]) {
+  int rest = c[0] == 0 && c[1] == 0 && c[2] == 0;
+  return rest ? alpha : (1.0 - alpha) * w / (1.0 - w0);
+}
+static double equilibrium_k(double alpha, double w0, double w, const int32_t c[3], double rho,
+                            const double u[3]) {
+  double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return rho * dr_phi(alpha, w, w0, c) + w * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+}
+
+void lbo_equilibrium_k(int lattice, double alpha, double rho, const double u[3], double *feq) {
+  int32_t c[QMAX][3], opp[QMAX];
+  double w[QMAX];
+  int Q = lbo_lattice(lattice, &c[0][0], w, opp);
+  double w0 = 0;
+  for (int i = 0; i < Q; ++i)
+    if (!c[i][0] && !c[i][1] && !c[i][2]) w0 = w[i];
+  for (int i = 0; i < Q; ++i) feq[i] = equilibrium_k(alpha, w0, w[i], c[i], rho, u);
+}
+
 /* ---- A_h: constant below h_min, (h_min/h)^3 decay up to h_max, 0 beyond -- */
 double lbo_A_h(double h, double A, double h_min, double h_max) {
   if (h <= h_min) return A;
@@ -138,10 +179,20 @@ static void collide(const lbo_params *p, int Q, int32_t (*c)[3], const double *w
   double Gh[3] = {0, 0, 0};
   if (g > 0)
     for (int a = 0; a < 3; ++a) Gh[a] = G[a] / g;
+  double w0 = 0, al1, al2;
+  for (int i = 0; i < Q; ++i)
+    if (!c[i][0] && !c[i][1] && !c[i][2]) w0 = w[i];
+  dr_alphas(p, w0, &al1, &al2);
   for (int i = 0; i < Q; ++i) {
     double fi = f1[i] + f2[i];
-    double feq = equilibrium_i(w[i], c[i], rho, u);
-    double feqF = equilibrium_i(w[i], c[i], rho, uF);
+    double feq, feqF;
+    if (dr_on(p)) {
+      feq = equilibrium_k(al1, w0, w[i], c[i], rho1, u) + equilibrium_k(al2, w0, w[i], c[i], rho2, u);
+      feqF = equilibrium_k(al1, w0, w[i], c[i], rho1, uF) + equilibrium_k(al2, w0, w[i], c[i], rho2, uF);
+    } else {
+      feq = equilibrium_i(w[i], c[i], rho, u);
+      feqF = equilibrium_i(w[i], c[i], rho, uF);
+    }
     double cG = c[i][0] * Gh[0] + c[i][1] * Gh[1] + c[i][2] * Gh[2];
     /* Omega1 (BGK) + forcing (EDM) + Omega2 (perturbation) */
     double pert = 0.5 * p->A_s * g * (w[i] * cG * cG - w[i] / 3.0);
@@ -149,7 +200,12 @@ static void collide(const lbo_params *p, int Q, int32_t (*c)[3], const double *w
     /* Omega3: recolouring with cos(phi_i) = c_i.G / (|c_i||G|) */
     double cnorm = sqrt((double)(c[i][0] * c[i][0] + c[i][1] * c[i][1] + c[i][2] * c[i][2]));
     double cosphi = (cnorm > 0) ? cG / cnorm : 0.0;
-    double a1 = rho1 / rho * fp + p->beta * rho1 * rho2 / rho * w[i] * cosphi;
+    double a1;
+    if (dr_on(p))
+      a1 = rho1 / rho * fp + p->beta * rho1 * rho2 / (rho * rho) *
+                                 (rho1 * dr_phi(al1, w[i], w0, c[i]) + rho2 * dr_phi(al2, w[i], w0, c[i])) * cosphi;
+    else
+      a1 = rho1 / rho * fp + p->beta * rho1 * rho2 / rho * w[i] * cosphi;
     o1[i] = a1;
     o2[i] = fp - a1;
   }
@@ -320,7 +376,7 @@ static int64_t find_feeder(const lbo_params *p, const uint8_t *type, int64_t n) 
 int lbo_set_geometry(lbo *h, const uint8_t *type, const double *rho1, const double *rho2,
                      const double *u) {
   const lbo_params *p = &h->p;
-  if (p->walls_y || p->nci_mode != 0) return -1;
+  if (p->walls_y || p->nci_mode != 0 || dr_on(p)) return -1;
   for (int64_t n = 0; n < h->N; ++n) {
     if (type[n] > LBO_OUTLET) return -1;
     if (type[n] == LBO_INLET || type[n] == LBO_OUTLET) {
@@ -373,9 +429,18 @@ int lbo_init_fields(lbo *h, const double *rho1, const double *rho2, const double
     double un[3] = {0, 0, 0};
     if (u)
       for (int a = 0; a < h->dim; ++a) un[a] = u[a * h->N + n];
+    double w0 = h->w[0], al1, al2;
+    for (int i = 0; i < h->Q; ++i)
+      if (!h->c[i][0] && !h->c[i][1] && !h->c[i][2]) w0 = h->w[i];
+    dr_alphas(&h->p, w0, &al1, &al2);
     for (int i = 0; i < h->Q; ++i) {
-      h->f1[i * h->N + n] = wall ? 0.0 : equilibrium_i(h->w[i], h->c[i], rho1[n], un);
-      h->f2[i * h->N + n] = wall ? 0.0 : equilibrium_i(h->w[i], h->c[i], rho2[n], un);
+      if (dr_on(&h->p)) {
+        h->f1[i * h->N + n] = wall ? 0.0 : equilibrium_k(al1, w0, h->w[i], h->c[i], rho1[n], un);
+        h->f2[i * h->N + n] = wall ? 0.0 : equilibrium_k(al2, w0, h->w[i], h->c[i], rho2[n], un);
+      } else {
+        h->f1[i * h->N + n] = wall ? 0.0 : equilibrium_i(h->w[i], h->c[i], rho1[n], un);
+        h->f2[i * h->N + n] = wall ? 0.0 : equilibrium_i(h->w[i], h->c[i], rho2[n], un);
+      }
     }
   }
   h->t = 0;
@@ -408,7 +473,7 @@ static void compute_psi(lbo *h) {
       r1 += h->f1[i * h->N + n];
       r2 += h->f2[i * h->N + n];
     }
-    h->psi[n] = (r1 - r2) / (r1 + r2);
+    h->psi[n] = dr_on(p) ? (r1 - p->rho_ratio * r2) / (r1 + p->rho_ratio * r2) : (r1 - r2) / (r1 + r2);
   }
   if (h->type) {
     /* inlets: their prescribed composition; outlets: their feeder's psi */

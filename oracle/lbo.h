@@ -53,6 +53,10 @@ typedef struct {
                                A_h of Eq. near_c); 1: continuous-NCI variant
                                (interpolated samples, continuous h, A_h shifted
                                to reach 0 at h_max)                          */
+  double rho_ratio;         /* density-ratio variant: gamma = rho_1^0/rho_2^0
+                               (> 0; 0 = equal densities, the paper's model) */
+  double alpha1;            /* rest fraction of component 1's equilibrium;
+                               alpha_2 = 1 - gamma (1 - alpha_1)             */
 } lbo_params;
 
 typedef struct lbo lbo;
@@ -65,7 +69,7 @@ void lbo_destroy(lbo *h);
 int64_t lbo_nodes(const lbo *h);
 
 /* Node types (N bytes, LBO_*) on the periodic lattice; requires walls_y = 0
- * and nci_mode = 0.  Every inlet/outlet needs a fluid neighbour along an axis
+ * and nci_mode = 0 and equal densities.  Every inlet/outlet needs a fluid neighbour along an axis
  * (its feeder).  Inlets take their composition rho1/(rho1+rho2) and velocity
  * u (dim*N, may be NULL) at their index, outlets their density rho1 + rho2.
  * Call before init_fields.  Returns 0, or -1 on an invalid mask. */
@@ -103,6 +107,8 @@ void lbo_diagnostics(lbo *h, double *psi, double *G, double *Frep, int32_t *hit,
 
 /* --- single-node operators, for unit pins ------------------------------- */
 void lbo_equilibrium(int lattice, double rho, const double u[3], double *feq);
+/* density-ratio variant: component equilibrium with rest fraction alpha */
+void lbo_equilibrium_k(int lattice, double alpha, double rho, const double u[3], double *feq);
 /* one collision at a node: inputs f1,f2 (Q each), gradient G and total force F;
  * outputs the post-recolouring populations. */
 void lbo_collide_node(const lbo_params *p, const double *f1, const double *f2,
