@@ -97,6 +97,20 @@ typedef struct {
                           A ((h_min/h)^3 - q)/(1 - q), q = (h_min/h_max)^3, so
                           F_rep is continuous in the fields.  Other values
                           are LB_EINVAL.                                      */
+  double rho_ratio;    /* density-ratio variant (an extension following the
+                          colour-gradient model the paper builds on): gamma =
+                          rho_1^0/rho_2^0 > 0; 0 = equal densities (the
+                          paper's model).  Component k relaxes towards
+                          E_i^k = rho_k phi_i^k + w_i rho_k (3 c.u + 4.5 (c.u)^2
+                          - 1.5 u.u), phi_0^k = alpha_k, phi_i^k = (1 - alpha_k)
+                          w_i/(1 - w_0), sound speed c_k^2 = (1 - alpha_k)/
+                          (3 (1 - w_0)); recolouring weights the colour term by
+                          (rho1 phi_i^1 + rho2 phi_i^2)/rho^2; psi =
+                          (rho1 - gamma rho2)/(rho1 + gamma rho2).              */
+  double alpha1;       /* rest fraction alpha_1 of component 1 (density-ratio
+                          variant); alpha_2 = 1 - gamma (1 - alpha_1) so that
+                          the reference densities have equal pressure.  Needs
+                          0 < alpha_1 < 1 and 0 < alpha_2 < 1 (LB_EINVAL)     */
 } lb_params;
 
 /* Observables of the current state, accumulated in FP64 in a fixed order:
@@ -204,7 +218,7 @@ int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double
  * +x, -y, +y, -z, +z (one is required).  The NCI probe also stops at inlet and
  * outlet nodes.  type, rho1, rho2 (N) and u (dim*N, may be NULL: zero inlet
  * velocity) are host arrays read during the call.  Requires walls_y == 0
- * (walls are solid nodes) and nci_mode == 0; call before lb_init_fields /
+ * (walls are solid nodes), nci_mode == 0 and rho_ratio == 0; call before lb_init_fields /
  * lb_set_populations (which then initialise fluid nodes only), once per
  * handle.  Errors: LB_EINVAL (bad type value, an inlet/outlet without a fluid
  * axis neighbour, invalid prescribed densities, walls_y or nci_mode set, a

@@ -163,6 +163,11 @@ int validate(const lb_params *p) {
   if (!(p->tau > 0.5)) return fail(LB_EINVAL, "tau must exceed 1/2");
   if (!(p->tau2 == 0.0 || p->tau2 > 0.5)) return fail(LB_EINVAL, "tau2 must be 0 or exceed 1/2");
   if (p->nci_mode != 0 && p->nci_mode != 1) return fail(LB_EINVAL, "nci_mode must be 0 or 1");
+  if (p->rho_ratio != 0.0) {
+    const double a2 = 1.0 - p->rho_ratio * (1.0 - p->alpha1);
+    if (!(p->rho_ratio > 0.0 && p->alpha1 > 0.0 && p->alpha1 < 1.0 && a2 > 0.0 && a2 < 1.0))
+      return fail(LB_EINVAL, "density ratio: need rho_ratio > 0 and 0 < alpha1, 1 - rho_ratio (1 - alpha1) < 1");
+  }
   if (!(p->beta >= 0.0 && p->beta <= 1.0)) return fail(LB_EINVAL, "beta must lie in [0,1]");
   if (!(p->A_s >= 0.0)) return fail(LB_EINVAL, "A_s must be >= 0");
   if (!(p->A_nci >= 0.0)) return fail(LB_EINVAL, "A_nci must be >= 0");
@@ -326,8 +331,19 @@ int lb_init_fields(lb_handle *h, const double *rho1, const double *rho2, const d
       const double cu = h->c[i][0] * v[0] + h->c[i][1] * v[1] + h->c[i][2] * v[2];
       const double P = 3.0 * cu + 4.5 * cu * cu - 1.5 * vv;  // E_i = w_i rho (1 + P)
       // total deviation f_i/w_i - 1 and component-1 share f1_i/w_i
-      xt[(size_t)i * N + n] = (rho - 1.0) + rho * P;
-      xc[(size_t)i * N + n] = rho1[n] * (1.0 + P);
+      if (h->p.rho_ratio > 0) {
+        // density-ratio variant: E_i^k = rho_k (phi_i^k + w_i P), phi_i^k/w_i = g_i^k
+        const bool rest = !h->c[i][0] && !h->c[i][1] && !h->c[i][2];
+        const double w0 = D == 2 ? 4.0 / 9.0 : 8.0 / 27.0;
+        const double a1 = h->p.alpha1, a2 = 1.0 - h->p.rho_ratio * (1.0 - a1);
+        const double g1 = rest ? a1 / w0 : (1.0 - a1) / (1.0 - w0);
+        const double g2 = rest ? a2 / w0 : (1.0 - a2) / (1.0 - w0);
+        xt[(size_t)i * N + n] = (rho1[n] * g1 + rho2[n] * g2 - 1.0) + rho * P;
+        xc[(size_t)i * N + n] = rho1[n] * (g1 + P);
+      } else {
+        xt[(size_t)i * N + n] = (rho - 1.0) + rho * P;
+        xc[(size_t)i * N + n] = rho1[n] * (1.0 + P);
+      }
     }
   }
   return upload_explicit(h, xt, xc);

@@ -222,6 +222,7 @@ int lb_set_geometry(lb_handle *h, const uint8_t *type, const double *rho1, const
   if (h->geom) return fail(LB_EINVAL, "lb_set_geometry: the handle already has a geometry");
   if (h->p.walls_y) return fail(LB_EINVAL, "lb_set_geometry: walls_y must be 0 (walls are solid nodes)");
   if (h->p.nci_mode != 0) return fail(LB_EINVAL, "lb_set_geometry: needs nci_mode 0");
+  if (h->p.rho_ratio != 0.0) return fail(LB_EINVAL, "lb_set_geometry: needs equal densities (rho_ratio 0)");
   const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz, Q = h->Q, D = h->D;
   const int64_t N = h->N;
   auto nbr = [&](int64_t n, int cx, int cy, int cz) -> int64_t {

@@ -143,6 +143,16 @@ inline lbk::Args<S, R> make_args(lb_handle *h, int in, int out) {
   for (int d = 0; d < 3; ++d) a.F[d] = (R)p.force[d];
   a.smax = (int)std::floor(p.h_max);
   a.smaxc = (int)std::ceil(p.h_max);
+  a.dr_on = p.rho_ratio > 0 ? 1 : 0;
+  a.dr_gamma = (R)(p.rho_ratio > 0 ? p.rho_ratio : 1.0);
+  if (p.rho_ratio > 0) {
+    const double w0 = h->D == 2 ? 4.0 / 9.0 : 8.0 / 27.0;
+    const double a2 = 1.0 - p.rho_ratio * (1.0 - p.alpha1);
+    a.dr_g1 = (R)((1.0 - p.alpha1) / (1.0 - w0) - 1.0);
+    a.dr_g2 = (R)((1.0 - a2) / (1.0 - w0) - 1.0);
+  } else {
+    a.dr_g1 = a.dr_g2 = (R)0;
+  }
   a.in = lbk::State<S, R>{(S *)h->s[in], h->s0[in], (R *)h->a[in], h->B[in]};
   a.out = lbk::State<S, R>{(S *)h->s[out], h->s0[out], (R *)h->a[out], h->B[out]};
   a.xt = h->xt;

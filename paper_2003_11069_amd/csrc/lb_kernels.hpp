@@ -111,6 +111,9 @@ struct Args {
   R F[3];
   int smax;           // floor(h_max)
   int smaxc;          // ceil(h_max), probe steps of the continuous-NCI variant
+  int dr_on;          // density-ratio variant
+  R dr_gamma;         // rho_1^0 / rho_2^0
+  R dr_g1, dr_g2;     // (1 - alpha_k)/(1 - w_0) - 1 (0 for equal densities)
   State<S, R> in, out;
   const double *xt;   // explicit first-step state: f_i/w_i - 1 (Q*N) or null
   const double *xc;   // explicit first-step state: f1_i/w_i (Q*N)
@@ -351,7 +354,10 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
       pull<D, S, R, SRC, COL_LDS, false, PX, PY, TS, GEOM>(A, x, y, z, n, ta, tB, lidx, f, nullptr, dr, r1,
                                                            j, gm);
       const R rho = (R)1 + dr;
-      st(A.psi, n, ((R)2 * r1 - rho) / rho);
+      if (A.dr_on)  // density-ratio variant: psi normalised by the reference densities
+        st(A.psi, n, (r1 - A.dr_gamma * (rho - r1)) / (r1 + A.dr_gamma * (rho - r1)));
+      else
+        st(A.psi, n, ((R)2 * r1 - rho) / rho);
       st(A.r1, n, r1);
     }
   }
@@ -668,7 +674,13 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       // of the two components' relaxation times (viscosity-ratio variant)
       const float om = A.two_tau ? (float)(r1 * irho * (A.tau_inv - A.tau2_inv) + A.tau2_inv) : tinv;
       const float omc = 1.f - om, om1 = om - 1.f;
-      const float cdr = om * drf - pg * (1.0f / 3.0f);
+      // density-ratio variant: the composition part of the equilibrium adds
+      // dnr = rho1 (g1 - 1) + rho2 (g2 - 1) to every non-rest direction (0
+      // for equal densities; the rest slot follows from mass closure)
+      // (FP32: with a density ratio the stored deviations of the lighter
+      // phase are O(1 - 1/gamma), so this rounding matches their storage's)
+      const float dnrf = (float)(r1 * A.dr_g1 + (rho - r1) * A.dr_g2);
+      const float cdr = om * (drf + dnrf) - pg * (1.0f / 3.0f);
       const uint32_t nb = n * (uint32_t)sizeof(S), NB = A.N * (uint32_t)sizeof(S);
       R sum_q = 0;
 #pragma unroll
@@ -718,7 +730,8 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       else stb_out<1>(A.out.s0, n * 4u, srest);
       const R dr_t = sum_q + (R)L::w(L::REST) * (R)srest;
       stb_out<2>(A.out.a, n * (uint32_t)sizeof(R), r1 / ((R)1 + dr_t));
-      const R b = A.beta * r1 * (rho - r1) * irho;
+      // recolouring weight (rho1 phi^1 + rho2 phi^2)/(rho w) = 1 + dnr/rho
+      const R b = A.beta * r1 * (rho - r1) * irho * ((R)1 + (R)dnrf * irho);
       stb_out<2>(A.out.B, n * 4u, (float)(b * Gh[0]));
       stb_out<2>(A.out.B + A.N, n * 4u, (float)(b * Gh[1]));
       if (D == 3) stb_out<2>(A.out.B + 2 * (size_t)A.N, n * 4u, (float)(b * Gh[2]));

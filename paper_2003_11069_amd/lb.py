@@ -37,7 +37,7 @@ class lb_params(C.Structure):
                 ("h_max", C.c_double), ("force", C.c_double * 3), ("storage", C.c_int32),
                 ("obs_every", C.c_int32), ("conv_window", C.c_int32), ("conv_m", C.c_int32),
                 ("conv_eps", C.c_double), ("tau2", C.c_double),
-                ("nci_mode", C.c_int32)]
+                ("nci_mode", C.c_int32), ("rho_ratio", C.c_double), ("alpha1", C.c_double)]
 
 
 class lb_obs(C.Structure):
@@ -172,6 +172,8 @@ class Params:
     conv_eps: float = 1e-4
     tau2: float = 0.0
     nci_mode: int = 0
+    rho_ratio: float = 0.0
+    alpha1: float = 0.0
 
     @classmethod
     def from_dict(cls, d: dict, **kw):

@@ -54,7 +54,9 @@ def test_lattice_tables(lat, Q):
 BAD = [dict(tau=0.5), dict(tau=0.3), dict(beta=1.5), dict(beta=-0.1), dict(nx=0), dict(nz=2),
        dict(h_min=5.0, h_max=4.0), dict(h_max=4.5), dict(h_min=0.0), dict(A_nci=-1.0),
        dict(storage=7), dict(lattice=5), dict(walls_y=1, ny=2), dict(A_s=-0.1), dict(tau2=0.4),
-       dict(tau2=-1.0), dict(nci_mode=2), dict(nci_mode=-1)]
+       dict(tau2=-1.0), dict(nci_mode=2), dict(nci_mode=-1),
+       dict(rho_ratio=2.0, alpha1=0.3), dict(rho_ratio=-1.0), dict(rho_ratio=2.0, alpha1=1.0),
+       dict(rho_ratio=3.0, alpha1=0.5)]
 
 
 @pytest.mark.parametrize("bad", BAD)
