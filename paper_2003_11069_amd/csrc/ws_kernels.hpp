@@ -466,22 +466,34 @@ struct UpBwdWeight {
 // Sums split partials [splits][M][Kw+1] in a fixed order into dW[m][k] (k < Kw)
 // and, for the ones column, db[c] = sum over rows m = c (mod Cb) of column Kw.
 // A block handles 16 output elements with 16 split groups: group g adds splits
-// g, g+16, g+32, ... in order, then the groups are combined by a fixed tree.
+// g, g+16, g+32, ... (four interleaved partial sums, combined in a fixed
+// order), then the groups are combined by a fixed tree.
 constexpr int RED_E = 16, RED_G = 16;
-static __global__ __launch_bounds__(256) void k_split_reduce(const float *partial, int splits, int M, int Kw,
-                                                             float *dW, float *db, int Cb) {
+static __global__ __launch_bounds__(RED_E * RED_G) void k_split_reduce(const float *partial, int splits, int M,
+                                                                        int Kw, float *dW, float *db, int Cb) {
   __shared__ float sh[RED_G][RED_E + 1];
   const int el = threadIdx.x % RED_E, gr = threadIdx.x / RED_E;
   const int e = blockIdx.x * RED_E + el;  // element: dW entries, then biases
   const int Nw = Kw + 1, nW = M * Kw;
+  auto column = [&](int m, int k) {
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int z = gr;
+    for (; z + 3 * RED_G < splits; z += 4 * RED_G) {
+      a0 += partial[((size_t)z * M + m) * Nw + k];
+      a1 += partial[((size_t)(z + RED_G) * M + m) * Nw + k];
+      a2 += partial[((size_t)(z + 2 * RED_G) * M + m) * Nw + k];
+      a3 += partial[((size_t)(z + 3 * RED_G) * M + m) * Nw + k];
+    }
+    for (; z < splits; z += RED_G) a0 += partial[((size_t)z * M + m) * Nw + k];
+    return (a0 + a1) + (a2 + a3);
+  };
   float acc = 0.f;
   if (e < nW) {
     const int m = e / Kw, k = e - m * Kw;
-    for (int z = gr; z < splits; z += RED_G) acc += partial[((size_t)z * M + m) * Nw + k];
+    acc = column(m, k);
   } else if (e < nW + Cb) {
     const int c = e - nW;
-    for (int m = c; m < M; m += Cb)
-      for (int z = gr; z < splits; z += RED_G) acc += partial[((size_t)z * M + m) * Nw + Kw];
+    for (int m = c; m < M; m += Cb) acc += column(m, Kw);
   }
   sh[gr][el] = acc;
   __syncthreads();

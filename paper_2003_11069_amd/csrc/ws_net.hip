@@ -210,6 +210,9 @@ void split_plan(int P, int M, int N, int &splits, int &chunk) {
   const int tiles = ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
   int s = std::max(1, 1024 / std::max(tiles, 1));
   s = std::min(s, std::max(1, P / (4 * BK)));
+  // the partials are written once and read back once: at most 8M floats
+  // (32 MB) of them unless that leaves fewer than 4 splits
+  s = std::min(s, std::max(4, (int)((8 << 20) / ((int64_t)M * N))));
   chunk = ((P + s - 1) / s + BK - 1) / BK * BK;
   splits = (P + chunk - 1) / chunk;
 }
@@ -245,8 +248,8 @@ WShape wshape(int Cout, int Kw1) { return Cout < 64 ? WShape{true, Kw1, Cout} : 
 
 void launch_split_reduce(ws_net *n, int splits, int M, int Kw, float *dW, float *db, int Cb) {
   const int64_t elems = (int64_t)M * Kw + Cb;
-  hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((elems + RED_E - 1) / RED_E)), dim3(256), 0, n->stream,
-                     n->scratch, splits, M, Kw, dW, db, Cb);
+  hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((elems + RED_E - 1) / RED_E)), dim3(RED_E * RED_G), 0,
+                     n->stream, n->scratch, splits, M, Kw, dW, db, Cb);
 }
 
 template <int KS, bool RELU, bool TR>
