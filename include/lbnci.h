@@ -193,6 +193,18 @@ int64_t lb_device_bytes(const lb_handle *h);
 int lb_profile(lb_handle *h, int enable);
 int lb_kernel_times(lb_handle *h, double *ms_phase, double *ms_main, int64_t *launches);
 
+/* A HIP stream for lb_create / lb_batch_create / lb_copy_probe: non-blocking
+ * (no implicit wait on the default stream), default priority, on the current
+ * device of the HIP runtime this library is linked against.  Handles on
+ * different streams run side by side (their kernels share the device); a
+ * stream created by another copy of the HIP runtime in the same process (one
+ * bundled with a Python framework, say) is not valid here.  *stream receives
+ * the hipStream_t.  lb_stream_destroy waits for the stream's work, then
+ * releases it; destroy every handle that uses the stream first.  Errors:
+ * LB_EINVAL for a NULL pointer, LB_EDEVICE from the runtime. */
+int lb_stream_create(void **stream);
+int lb_stream_destroy(void *stream);
+
 /* Achievable-bandwidth reference: a plain streaming copy of `bytes` bytes
  * (16-byte vector loads/stores) repeated `iters` times on the current device;
  * returns the average per-copy duration (ms) and the read+write rate (GB/s).

@@ -629,13 +629,15 @@ int lb_droplets(lb_handle *h, lb_droplet_stats *stats, int32_t *label, int64_t c
   const size_t count = (size_t)cnt[0];
   std::vector<int64_t> vol(count);
   std::vector<double> cen(3 * count);
+  // copies on the handle's stream only, so that handles on other streams keep running
   if (count) {
-    HIP_TRY(hipMemcpy(vol.data(), a.volume, 8 * count, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(cen.data(), a.centroid, 8 * 3 * count, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(vol.data(), a.volume, 8 * count, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(cen.data(), a.centroid, 8 * 3 * count, hipMemcpyDeviceToHost, h->stream));
   }
   const size_t ncopy = std::min(count, (size_t)cap);
-  if (label) HIP_TRY(hipMemcpy(label, a.parent, 4 * (size_t)h->N, hipMemcpyDeviceToHost));
-  if (root && ncopy) HIP_TRY(hipMemcpy(root, a.root, 8 * ncopy, hipMemcpyDeviceToHost));
+  if (label) HIP_TRY(hipMemcpyAsync(label, a.parent, 4 * (size_t)h->N, hipMemcpyDeviceToHost, h->stream));
+  if (root && ncopy) HIP_TRY(hipMemcpyAsync(root, a.root, 8 * ncopy, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
   if (volume && ncopy) std::memcpy(volume, vol.data(), 8 * ncopy);
   if (centroid && ncopy) std::memcpy(centroid, cen.data(), 8 * 3 * ncopy);
   if (stats) {

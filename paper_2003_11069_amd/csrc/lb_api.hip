@@ -560,6 +560,21 @@ int lb_kernel_times(lb_handle *h, double *ms_phase, double *ms_main, int64_t *la
   return LB_OK;
 }
 
+int lb_stream_create(void **stream) {
+  if (!stream) return fail(LB_EINVAL, "lb_stream_create: NULL argument");
+  hipStream_t st = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  *stream = (void *)st;
+  return LB_OK;
+}
+
+int lb_stream_destroy(void *stream) {
+  if (!stream) return fail(LB_EINVAL, "lb_stream_destroy: NULL stream");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipStreamDestroy((hipStream_t)stream));
+  return LB_OK;
+}
+
 int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double *gbps) {
   if (bytes < 16 || iters < 1) return fail(LB_EINVAL, "bad copy-probe size");
   hipStream_t st = (hipStream_t)hip_stream;

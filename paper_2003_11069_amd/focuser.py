@@ -53,38 +53,82 @@ def reduce_samples(samples, xc):
     return v_main, crossings, crossings / span
 
 
+class _Run:
+    """One flow-focuser handle and its samples (droplet tables and the flux
+    through x_c), stepped by ``run`` alone or by ``sweep`` beside others."""
+
+    def __init__(self, scale, phi, u_c, A_s, N_c, W_out, storage, stream=None):
+        self.case = case = synth.flow_focuser_2d(scale=scale, phi=phi, u_c=u_c, A_s=A_s, N_c=N_c, W_out=W_out)
+        p = case.params
+        self.phi, self.nx, self.ny = phi, p["nx"], p["ny"]
+        self.lat = _lb.Lattice(_lb.Params.from_dict(p, storage=_lb.STORAGE[storage]), stream=stream)
+        self.lat.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
+        self.lat.init_fields(case.rho1, case.rho2, case.u)
+        self.x0 = case.info["x_out0"]
+        self.xc = self.x0 + (self.nx - self.x0) // 4
+        self.samples = []       # (t, centroids[:, (x, y)], volumes)
+        self.flux = []
+
+    def sample(self):
+        d = self.lat.droplets(labels=False)
+        cen, vol = d["centroids"], d["volumes"]
+        keep = cen[:, 0] > self.x0
+        self.samples.append((self.lat.t, cen[keep, :2].copy(), vol[keep].copy()))
+        r1, r2, u = self.lat.fields()
+        nx, ny, xc = self.nx, self.ny, self.xc
+        self.flux.append(float((r1.reshape(ny, nx)[:, xc] * u[0].reshape(ny, nx)[:, xc]).sum()))
+
+    def result(self, steps, t_skip, every, elapsed, keep_samples):
+        info = self.case.info
+        v_main, crossings, nu = reduce_samples(self.samples, self.xc)
+        return {"nx": self.nx, "ny": self.ny, "fluid_nodes": int((info["type"] == synth.FLUID).sum()),
+                "phi": self.phi, "u_c": info["u_c"], "u_d": info["u_d"],
+                "steps": steps, "t_skip": t_skip, "every": every, "x_c": int(self.xc),
+                "V_d": v_main, "droplets_crossed": crossings, "nu": nu, "Q_d": nu * v_main,
+                "flux_xc_mean": float(np.mean(self.flux)) if self.flux else 0.0,
+                "inlet_dispersed_flux": info["u_d"] * info["H"],
+                "seconds": elapsed, "graphs": self.lat.graphs,
+                "samples": self.samples if keep_samples else None,
+                "flux_samples": self.flux if keep_samples else None}
+
+
 def run(scale=2.0, phi=0.25, u_c=0.004, A_s=0.1, N_c=0.1, W_out=64, steps=60000, t_skip=20000,
         every=250, storage="fp32", keep_samples=False):
-    case = synth.flow_focuser_2d(scale=scale, phi=phi, u_c=u_c, A_s=A_s, N_c=N_c, W_out=W_out)
-    p = case.params
-    nx, ny = p["nx"], p["ny"]
-    lat = _lb.Lattice(_lb.Params.from_dict(p, storage=_lb.STORAGE[storage]))
-    lat.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
-    lat.init_fields(case.rho1, case.rho2, case.u)
-    x0 = case.info["x_out0"]
-    xc = x0 + (nx - x0) // 4
-    fluid = int((case.info["type"] == synth.FLUID).sum())
+    r = _Run(scale, phi, u_c, A_s, N_c, W_out, storage)
     t0 = time.perf_counter()
-    lat.step(t_skip)
-    samples = []       # (t, [(x, y, volume)])
-    flux = []
-    while lat.t < steps:
-        lat.step(every)
-        d = lat.droplets(labels=False)
-        cen, vol = d["centroids"], d["volumes"]
-        keep = cen[:, 0] > x0
-        samples.append((lat.t, cen[keep, :2].copy(), vol[keep].copy()))
-        r1, r2, u = lat.fields()
-        flux.append(float((r1.reshape(ny, nx)[:, xc] * u[0].reshape(ny, nx)[:, xc]).sum()))
+    r.lat.step(t_skip)
+    while r.lat.t < steps:
+        r.lat.step(every)
+        r.sample()
+    return r.result(steps, t_skip, every, time.perf_counter() - t0, keep_samples)
+
+
+def sweep(phis, scale=2.0, u_c=0.004, A_s=0.1, N_c=0.1, W_out=64, steps=60000, t_skip=20000, every=250,
+          storage="fp32", keep_samples=False):
+    """``run`` for every flow ratio in ``phis`` at once: one handle per phi,
+    each on its own HIP stream (default priority), stepped in lockstep.  One
+    focuser of this size fills well under one wave per SIMD, so the handles'
+    kernels run side by side on the idle compute units; each handle's
+    arithmetic is that of ``run`` (the same results, bit for bit).  Returns
+    one result per phi, each with the wall time of the whole sweep."""
+    streams = [_lb.Stream() for _ in phis]
+    runs = [_Run(scale, phi, u_c, A_s, N_c, W_out, storage, stream=st.handle)
+            for phi, st in zip(phis, streams)]
+    t0 = time.perf_counter()
+    for r in runs:
+        r.lat.step(t_skip)
+    while runs[0].lat.t < steps:
+        for r in runs:          # enqueue every handle's steps before the first sample waits
+            r.lat.step(every)
+        for r in runs:
+            r.sample()
     elapsed = time.perf_counter() - t0
-    v_main, crossings, nu = reduce_samples(samples, xc)
-    return {"nx": nx, "ny": ny, "fluid_nodes": fluid, "phi": phi, "u_c": u_c, "u_d": case.info["u_d"],
-            "steps": steps, "t_skip": t_skip, "every": every, "x_c": int(xc),
-            "V_d": v_main, "droplets_crossed": crossings, "nu": nu, "Q_d": nu * v_main,
-            "flux_xc_mean": float(np.mean(flux)) if flux else 0.0,
-            "inlet_dispersed_flux": case.info["u_d"] * case.info["H"],
-            "seconds": elapsed, "graphs": lat.graphs,
-            "samples": samples if keep_samples else None, "flux_samples": flux if keep_samples else None}
+    out = [r.result(steps, t_skip, every, elapsed, keep_samples) for r in runs]
+    for r in runs:
+        r.lat.close()
+    for st in streams:
+        st.close()
+    return out
 
 
 def main(argv=None):
@@ -95,9 +139,14 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=250)
     ap.add_argument("--u-c", type=float, default=0.004)
     ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--concurrent", action="store_true", help="all phi at once, one HIP stream each")
     a = ap.parse_args(argv)
-    for phi in a.phi:
-        r = run(phi=phi, u_c=a.u_c, steps=a.steps, t_skip=a.skip, every=a.every, storage=a.storage)
+    if a.concurrent:
+        res = sweep(a.phi, u_c=a.u_c, steps=a.steps, t_skip=a.skip, every=a.every, storage=a.storage)
+    else:
+        res = (run(phi=phi, u_c=a.u_c, steps=a.steps, t_skip=a.skip, every=a.every, storage=a.storage)
+               for phi in a.phi)
+    for r in res:
         r.pop("samples"); r.pop("flux_samples")
         print(json.dumps(r), flush=True)
 

@@ -2,14 +2,14 @@
 
 Argument marshalling only: every step of the lattice Boltzmann update runs in
 the library's HIP kernels.  There is no CPU fallback; a missing library or
-GPU raises.  Streams come from PyTorch when it is available (the handle then
-enqueues its work on ``torch.cuda.current_stream()``).
+GPU raises.  Work goes to the default HIP stream unless a stream of the
+library's own runtime is given (``Stream``): a Python framework that bundles
+its own HIP runtime hands out streams that are not valid in this one.
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
-import sys
 from dataclasses import dataclass, field, asdict
 
 import numpy as np
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
         "lb_profile": ([vp, C.c_int], C.c_int),
         "lb_kernel_times": ([vp, dp, dp, P(C.c_int64)], C.c_int),
         "lb_copy_probe": ([C.c_int64, C.c_int, vp, dp, dp], C.c_int),
+        "lb_stream_create": ([P(vp)], C.c_int),
+        "lb_stream_destroy": ([vp], C.c_int),
         "lb_droplets": ([vp, P(lb_droplet_stats), ip, C.c_int64, P(C.c_int64), P(C.c_int64), dp],
                         C.c_int),
         "lb_vorticity": ([vp, dp], C.c_int),
@@ -121,16 +123,38 @@ def _ip(a):
 
 
 def current_stream_handle():
-    """hipStream_t of torch's current stream when the caller already uses
-    torch (torch provides streams only), else 0 = the default stream."""
-    torch = sys.modules.get("torch")
-    if torch is not None:
+    """The stream a handle uses when none is given: 0, the default stream."""
+    return 0
+
+
+class Stream:
+    """A non-blocking HIP stream of the library's runtime (lb_stream_create),
+    default priority.  ``handle`` is the hipStream_t to pass as ``stream=``;
+    close() (or leaving a ``with`` block) waits for its work and releases it,
+    after the handles that use it are closed."""
+
+    def __init__(self):
+        self.lib = load_library()
+        h = C.c_void_p()
+        _check(self.lib.lb_stream_create(C.byref(h)))
+        self.handle = h.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(self.lib.lb_stream_destroy(C.c_void_p(self.handle)))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
         try:
-            if torch.cuda.is_available():
-                return torch.cuda.current_stream().cuda_stream
+            self.close()
         except Exception:
             pass
-    return 0
 
 
 def copy_probe(nbytes: int, iters: int = 20, stream: int | None = None):

@@ -74,6 +74,15 @@ def test_batch_rejects_continuous_nci():
     assert ei.value.code == -1 and "nci_mode" in str(ei.value)
 
 
+def test_stream_calls_reject_null():
+    """The argument checks of lb_stream_create / lb_stream_destroy precede
+    any runtime call."""
+    lib = P.load_library()
+    assert lib.lb_stream_create(None) == -1
+    assert lib.lb_stream_destroy(None) == -1
+    assert lbmod.current_stream_handle() == 0
+
+
 def test_last_error_message():
     with pytest.raises(P.LBError):
         P.Lattice(P.Params(tau=0.4))

@@ -42,3 +42,21 @@ def test_generation_statistics_match_the_oracle():
     assert r["flux_xc_mean"] == pytest.approx(ref["flux_xc_mean"], rel=0.01)
     assert r["nu"] == pytest.approx(ref["nu"], rel=0.25)
     assert r["V_d"] == pytest.approx(ref["V_d"], rel=0.25)
+
+
+def test_concurrent_sweep_equals_separate_runs():
+    """Handles on their own streams, stepped side by side, compute exactly
+    what each computes alone: the same droplet tables and flux samples."""
+    import numpy as np
+
+    phis = [0.15, 0.25, 0.35]
+    kw = dict(steps=26000, t_skip=20000, every=500, keep_samples=True)
+    say(f"[gpu] flow-focuser sweep, phi {phis} on three streams, against separate runs")
+    both = focuser.sweep(phis, **kw)
+    for phi, s in zip(phis, both):
+        r = focuser.run(phi=phi, **kw)
+        assert len(s["samples"]) == len(r["samples"]) == 12
+        for (ta, ca, va), (tb, cb, vb) in zip(s["samples"], r["samples"]):
+            assert ta == tb and np.array_equal(ca, cb) and np.array_equal(va, vb)
+        assert s["flux_samples"] == r["flux_samples"]
+        assert (s["V_d"], s["droplets_crossed"]) == (r["V_d"], r["droplets_crossed"])
