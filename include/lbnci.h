@@ -233,8 +233,9 @@ int lb_copy_probe(int64_t bytes, int iters, void *hip_stream, double *ms, double
  * (walls are solid nodes), nci_mode == 0 and rho_ratio == 0; call before lb_init_fields /
  * lb_set_populations (which then initialise fluid nodes only), once per
  * handle.  Errors: LB_EINVAL (bad type value, an inlet/outlet without a fluid
- * axis neighbour, invalid prescribed densities, walls_y or nci_mode set, a
- * second call), LB_ENOMEM, LB_EDEVICE.  Single lattices only (not batches). */
+ * axis neighbour, invalid prescribed densities, walls_y or nci_mode set, an
+ * extent not above h_max while A_nci > 0, a second call), LB_ENOMEM,
+ * LB_EDEVICE.  Single lattices only (not batches). */
 #define LB_NODE_FLUID 0
 #define LB_NODE_SOLID 1
 #define LB_NODE_INLET 2

@@ -7,9 +7,9 @@
 // GEO_NONFLUID), non-fluid nodes are skipped, pulls from solid sources use the
 // bounce-back rule (the colliding fluid node writes its reflected populations
 // into the solid node's slots, as for wall rows), and the NCI probe stops at
-// non-fluid nodes.  Between k_phase and k_main two small kernels give outlet
+// non-fluid nodes.  Between k_phase and k_main one small kernel gives outlet
 // nodes their feeder's psi and solid nodes the weighted mean psi of their
-// non-solid neighbours; after k_main a third sets every inlet/outlet node's
+// non-solid neighbours; after k_main a second sets every inlet/outlet node's
 // post-collision state from its feeder (the equilibrium of the boundary
 // condition), so the next pull treats them like any node.
 #include "lb_internal.hpp"
@@ -34,28 +34,34 @@ __device__ __forceinline__ uint32_t neighbour(int nx, int ny, int nz, uint32_t n
          (uint32_t)nx * ((uint32_t)wrapi(y + cy, ny) + (uint32_t)ny * (D == 3 ? wrapi(z + cz, nz) : 0));
 }
 
-// psi of an outlet: its feeder's
-template <typename R>
-__global__ __launch_bounds__(256) void k_psi_outlets(R *psi, const int32_t *pairs, int n) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  psi[pairs[2 * k]] = psi[pairs[2 * k + 1]];
-}
-
-// psi of a solid node: w_i-weighted mean over its non-solid neighbours
+// psi of the boundary nodes, after k_phase, in one pass: an outlet takes its
+// feeder's psi; a solid node the w_i-weighted mean over its non-solid
+// neighbours, an outlet neighbour entering with its feeder's psi (the value
+// it receives in the same pass), so no thread reads a slot another writes.
+// Threads [0, n_out) handle the (outlet, feeder) pairs, the rest the solids.
 template <int D, typename R>
-__global__ __launch_bounds__(256) void k_psi_solids(R *psi, const uint32_t *nbm, const int32_t *nodes, int n,
-                                                    int nx, int ny, int nz) {
+__global__ __launch_bounds__(256) void k_psi_boundary(R *psi, const uint32_t *nbm, const int32_t *pairs,
+                                                      int n_out, const int32_t *solids, int n_sol, int nx,
+                                                      int ny, int nz) {
   using L = Lat<D>;
   const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  const uint32_t s = (uint32_t)nodes[k];
+  if (k < n_out) {
+    psi[pairs[2 * k]] = psi[pairs[2 * k + 1]];
+    return;
+  }
+  if (k - n_out >= n_sol) return;
+  const uint32_t s = (uint32_t)solids[k - n_out];
   R sw = 0, sp = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     if (i == L::REST) continue;
-    const uint32_t m = neighbour<D>(nx, ny, nz, s, L::cx(i), L::cy(i), L::cz(i));
-    if (nbm[m] & GEO_SOLID) continue;
+    uint32_t m = neighbour<D>(nx, ny, nz, s, L::cx(i), L::cy(i), L::cz(i));
+    const uint32_t mm = nbm[m];
+    if (mm & GEO_SOLID) continue;
+    if (mm & GEO_OUTLET) {
+      const int a = (int)(mm & GEO_FEEDER), sg = (a & 1) ? 1 : -1;
+      m = neighbour<D>(nx, ny, nz, m, a < 2 ? sg : 0, (a >> 1) == 1 ? sg : 0, a >= 4 ? sg : 0);
+    }
     sw += (R)L::w(i);
     sp += (R)L::w(i) * psi[m];
   }
@@ -152,12 +158,10 @@ int run_pass_geom(lb_handle *h, int mode, double *o0, double *o1, double *o2, in
     for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&e[k]));
   if (h->explicit_src) launch_phase_geom<D, S, R, EXPLICIT>(h, a, e[0], e[1]);
   else launch_phase_geom<D, S, R, PULL>(h, a, e[0], e[1]);
-  if (h->n_psi_out)
-    hipLaunchKernelGGL(k_psi_outlets<R>, dim3((h->n_psi_out + 255) / 256), dim3(256), 0, h->stream, a.psi,
-                       h->psi_out, h->n_psi_out);
-  if (h->n_psi_solid)
-    hipLaunchKernelGGL((k_psi_solids<D, R>), dim3((h->n_psi_solid + 255) / 256), dim3(256), 0, h->stream, a.psi,
-                       h->nbm, h->psi_solid, h->n_psi_solid, h->p.nx, h->p.ny, h->p.nz);
+  const int n_psi = h->n_psi_out + h->n_psi_solid;
+  if (n_psi)
+    hipLaunchKernelGGL((k_psi_boundary<D, R>), dim3((n_psi + 255) / 256), dim3(256), 0, h->stream, a.psi, h->nbm,
+                       h->psi_out, h->n_psi_out, h->psi_solid, h->n_psi_solid, h->p.nx, h->p.ny, h->p.nz);
   if (h->explicit_src) launch_main_mode<D, S, R, EXPLICIT>(h, mode, a, e[2], e[3]);
   else launch_main_mode<D, S, R, PULL>(h, mode, a, e[2], e[3]);
   if (step && h->n_bc)
@@ -225,6 +229,9 @@ int lb_set_geometry(lb_handle *h, const uint8_t *type, const double *rho1, const
   if (h->p.rho_ratio != 0.0) return fail(LB_EINVAL, "lb_set_geometry: needs equal densities (rho_ratio 0)");
   const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz, Q = h->Q, D = h->D;
   const int64_t N = h->N;
+  const int reach = (int)std::ceil(h->p.h_max);  // the probe wraps at most once
+  if (h->p.A_nci > 0.0 && (nx <= reach || ny <= reach || (D == 3 && nz <= reach)))
+    return fail(LB_EINVAL, "lb_set_geometry: every extent must exceed the probe reach h_max = %g", h->p.h_max);
   auto nbr = [&](int64_t n, int cx, int cy, int cz) -> int64_t {
     const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
     const int xx = ((x + cx) % nx + nx) % nx, yy = ((y + cy) % ny + ny) % ny, zz = ((z + cz) % nz + nz) % nz;
@@ -253,10 +260,14 @@ int lb_set_geometry(lb_handle *h, const uint8_t *type, const double *rho1, const
         if (type[nbr(n, -h->c[i][0], -h->c[i][1], -h->c[i][2])] == LB_NODE_SOLID) m |= 1u << i;
     } else {
       int64_t feeder = -1;
+      uint32_t axis = 0;
       for (int k = 0; k < 6 && feeder < 0; ++k) {
         if (nz == 1 && dirs[k][2] != 0) continue;
         const int64_t f = nbr(n, dirs[k][0], dirs[k][1], dirs[k][2]);
-        if (type[f] == LB_NODE_FLUID) feeder = f;
+        if (type[f] == LB_NODE_FLUID) {
+          feeder = f;
+          axis = (uint32_t)k;
+        }
       }
       if (feeder < 0)
         return fail(LB_EINVAL, "lb_set_geometry: inlet/outlet node %lld has no fluid neighbour along an axis",
@@ -280,6 +291,7 @@ int lb_set_geometry(lb_handle *h, const uint8_t *type, const double *rho1, const
       else {
         pout.push_back((int32_t)n);
         pout.push_back((int32_t)feeder);
+        m |= GEO_OUTLET | axis;
       }
     }
     mask[(size_t)n] = m;

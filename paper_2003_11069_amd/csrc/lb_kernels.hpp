@@ -129,6 +129,9 @@ struct Args {
 
 // Flags of the geometry mask word.
 constexpr uint32_t GEO_SOLID = 1u << 30, GEO_NONFLUID = 1u << 31;
+// outlet nodes: GEO_OUTLET, and bits 0-2 hold the axis direction of the
+// feeder (0..5 for -x, +x, -y, +y, -z, +z)
+constexpr uint32_t GEO_OUTLET = 1u << 29, GEO_FEEDER = 7u;
 
 enum Mode { STEP = 0, STEP_OBS = 1, OBSERVE = 2, FIELDS = 3, POPS = 4, DIAG = 5 };
 enum Src { PULL = 0, EXPLICIT = 1 };
@@ -138,6 +141,9 @@ __device__ __forceinline__ int wrapi(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
 }
+
+// periodic wrap of v in [-n, 2n) (one step outside the lattice at most)
+__device__ __forceinline__ int wrap_near(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // Maps the hardware block id to a logical tile id so that the tiles of one
 // XCD (blocks are dealt round-robin over the 8 XCDs) form a contiguous range.
@@ -325,6 +331,13 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
   constexpr int TS = PhaseTile<D, TZP>::TS;
   const int x0 = bx * 64, y0 = by * 4, z0 = (D == 3) ? bz * TZP : 0;
   const int tid = threadIdx.x + 64 * threadIdx.y;
+  // geometry: the first node's mask word is loaded before the LDS fill, so
+  // its non-fluid test below waits for nothing (geometries have no wall rows)
+  uint32_t gm0 = 0u;
+  if constexpr (GEOM) {
+    const int xg = x0 + threadIdx.x, yg = y0 + threadIdx.y;
+    if (xg < A.nx && yg < A.ny) gm0 = ld(A.nbm, (uint32_t)xg + (uint32_t)A.nx * ((uint32_t)yg + (uint32_t)A.ny * z0));
+  }
   if (SRC == PULL) {
     __syncthreads();
     for (int k = tid; k < TS; k += 256) {
@@ -346,7 +359,7 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
       const int z = z0 + tz;
       if (z >= A.nz) break;
       const uint32_t n = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
-      const uint32_t gm = GEOM ? ld(A.nbm, n) : 0u;
+      const uint32_t gm = GEOM ? (tz == 0 ? gm0 : ld(A.nbm, n)) : 0u;
       if (GEOM && (gm & GEO_NONFLUID)) continue;
       const int lidx = (threadIdx.x + 1) + PX * ((threadIdx.y + 1) + PY * ((D == 3) ? tz + 1 : 0));
       float f[Lat<D>::Q];
@@ -452,6 +465,13 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
   constexpr int NT = 64 * BY;
   const int x0 = bx * 64, y0 = by * BY, z0 = (D == 3) ? bz * TZ : 0;
   const int tid = threadIdx.x + 64 * threadIdx.y;
+  // geometry: the first node's mask word is loaded before the psi fill, so
+  // its non-fluid test below waits for nothing (geometries have no wall rows)
+  uint32_t gm0 = 0u;
+  if constexpr (GEOM) {
+    const int xg = x0 + threadIdx.x, yg = y0 + threadIdx.y;
+    if (xg < A.nx && yg < A.ny) gm0 = ld(A.nbm, (uint32_t)xg + (uint32_t)A.nx * ((uint32_t)yg + (uint32_t)A.ny * z0));
+  }
 
   // stage psi(tile + halo); wall rows read their fluid neighbour (copy rule)
   __syncthreads();
@@ -474,7 +494,7 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
     const int z = z0 + tz;
     if (!xy_ok || z >= A.nz) continue;
     const uint32_t n = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
-    const uint32_t gm = GEOM ? ld(A.nbm, n) : 0u;
+    const uint32_t gm = GEOM ? (tz == 0 ? gm0 : ld(A.nbm, n)) : 0u;
     if (GEOM && (gm & GEO_NONFLUID)) continue;
     const int lx = threadIdx.x + H, ly = threadIdx.y + H, lz = (D == 3) ? tz + H : 0;
     auto T = [&](int ox, int oy, int oz) -> R {
@@ -555,23 +575,22 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         const int oz = (D == 3) ? (int)round_away((R)s * nn[2]) : 0;
         const int yt = y + oy;
         if (A.walls && (yt <= 0 || yt >= A.ny - 1)) break;
-        if (GEOM) {  // the probe stops at any node that is not fluid
-          const uint32_t ns = (uint32_t)wrapi(x + ox, A.nx) +
-                              (uint32_t)A.nx * ((uint32_t)wrapi(yt, A.ny) +
-                                                (uint32_t)A.ny * ((D == 3) ? wrapi(z + oz, A.nz) : 0));
-          if (ld(A.nbm, ns) & GEO_NONFLUID) break;
-        }
         R pv;
         if constexpr (GEOM) {
-          // LDS value read at clamped offsets, the global value only beyond
-          // the halo (keeps the two loads apart)
+          // the probe stops at any node that is not fluid; the mask word and
+          // psi of the sample are loaded together.  LDS value read at clamped
+          // offsets, the global value only beyond the halo (keeps the two
+          // loads apart)
+          // (a geometry's extents exceed the probe reach: one wrap at most)
+          const int xt = wrap_near(x + ox, A.nx);
+          const int zt = (D == 3) ? wrap_near(z + oz, A.nz) : 0;
+          const uint32_t ns =
+              (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)wrap_near(yt, A.ny) + (uint32_t)A.ny * zt);
+          const uint32_t ms = ld(A.nbm, ns);
           const bool inside = abs(ox) <= H && abs(oy) <= H && abs(oz) <= H;
           pv = T(min(max(ox, -H), H), min(max(oy, -H), H), min(max(oz, -H), H));
-          if (!inside) {
-            const int xt = wrapi(x + ox, A.nx);
-            const int zt = (D == 3) ? wrapi(z + oz, A.nz) : 0;
-            pv = ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)wrapi(yt, A.ny) + (uint32_t)A.ny * zt));
-          }
+          if (!inside) pv = ld(A.psi, ns);
+          if (ms & GEO_NONFLUID) break;
         } else if (abs(ox) <= H && abs(oy) <= H && abs(oz) <= H) {
           pv = T(ox, oy, oz);
         } else {
@@ -682,6 +701,8 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       const float dnrf = (float)(r1 * A.dr_g1 + (rho - r1) * A.dr_g2);
       const float cdr = om * (drf + dnrf) - pg * (1.0f / 3.0f);
       const uint32_t nb = n * (uint32_t)sizeof(S), NB = A.N * (uint32_t)sizeof(S);
+      Offs go{};  // geometry: wrapped byte offsets of the neighbours (periodic)
+      if constexpr (GEOM) go = make_offs<D, (uint32_t)sizeof(S)>(A.nx, A.ny, A.nz, 0, x, y, z);
       R sum_q = 0;
 #pragma unroll
       for (int i = 0; i < L::REST; ++i) {
@@ -710,12 +731,11 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         };
         if constexpr (GEOM) {
           // populations heading into a solid node x + c_d: reflected copy in
-          // its slot opp(d) (bit k of gm: the source x - c_k is solid)
+          // its slot opp(d) (bit k of gm: the source x - c_k is solid); x + c_d
+          // is the pull source of -c_d, so its byte offset is go.*[1 - c_d]
           auto ghost_g = [&](int d, int dcx, int dcy, int dcz, S q) {
-            const uint32_t nw = (uint32_t)wrapi(x + dcx, A.nx) +
-                                (uint32_t)A.nx * ((uint32_t)wrapi(y + dcy, A.ny) +
-                                                  (uint32_t)A.ny * ((D == 3) ? wrapi(z + dcz, A.nz) : 0));
-            stb_out<1>(A.out.s, nw * (uint32_t)sizeof(S) + (uint32_t)L::opp(d) * NB, q);
+            const uint32_t nwb = nb + go.x[1 - dcx] + go.y[1 - dcy] + go.z[1 - dcz];
+            stb_out<1>(A.out.s, nwb + (uint32_t)L::opp(d) * NB, q);
           };
           if ((gm >> io) & 1u) ghost_g(i, icx, icy, icz, q_i);
           if ((gm >> i) & 1u) ghost_g(io, -icx, -icy, -icz, q_o);

@@ -140,3 +140,12 @@ def test_invalid_geometries_are_rejected():
     g.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
     with pytest.raises(P.LBError):  # once per handle
         g.set_geometry(case.info["type"], case.rho1, case.rho2, case.u)
+    # with the NCI force on, every extent must exceed the probe reach h_max
+    fluid = np.zeros(20 * 4, np.uint8)
+    r = np.full(20 * 4, 0.5)
+    g = P.Lattice(P.Params(nx=20, ny=4, A_nci=0.01, h_min=1.0, h_max=4.0))
+    with pytest.raises(P.LBError) as ei:
+        g.set_geometry(fluid, r, r)
+    assert "probe reach" in str(ei.value)
+    g = P.Lattice(P.Params(nx=20, ny=4, A_nci=0.01, h_min=1.0, h_max=3.0))
+    g.set_geometry(fluid, r, r)
