@@ -723,11 +723,8 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         // populations heading into a wall: reflected copy into the wall row,
         // node x + c_d, slot opp(d) (direction i has c_y = icy, opp(i) -icy)
         auto ghost = [&](int d, int dcx, int dcy, int dcz, S q) {
-          const int xw = wrapi(x + dcx, A.nx);
-          const int zw = (D == 3) ? wrapi(z + dcz, A.nz) : 0;
-          const uint32_t nw =
-              (uint32_t)xw + (uint32_t)A.nx * ((uint32_t)(y + dcy) + (uint32_t)A.ny * zw);
-          stb_out<1>(A.out.s, nw * (uint32_t)sizeof(S) + (uint32_t)L::opp(d) * NB, q);
+          const Offs wo = make_offs<D, (uint32_t)sizeof(S)>(A.nx, A.ny, A.nz, 1, x, y, z);
+          stb_out<1>(A.out.s, nb + wo.x[1 - dcx] + wo.y[1 - dcy] + wo.z[1 - dcz] + (uint32_t)L::opp(d) * NB, q);
         };
         if constexpr (GEOM) {
           // populations heading into a solid node x + c_d: reflected copy in
