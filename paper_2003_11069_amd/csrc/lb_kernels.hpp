@@ -327,7 +327,7 @@ struct PhaseTile {
 template <int D, typename S, typename R, int SRC, int TZP, int GEOM = 0>
 __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, int bz, R *ta,
                                            float *tB) {
-  constexpr int PX = PhaseTile<D, TZP>::PX, PY = PhaseTile<D, TZP>::PY;
+  constexpr int PX = PhaseTile<D, TZP>::PX, PY = PhaseTile<D, TZP>::PY, PZ = PhaseTile<D, TZP>::PZ;
   constexpr int TS = PhaseTile<D, TZP>::TS;
   const int x0 = bx * 64, y0 = by * 4, z0 = (D == 3) ? bz * TZP : 0;
   const int tid = threadIdx.x + 64 * threadIdx.y;
@@ -339,18 +339,41 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
     if (xg < A.nx && yg < A.ny) gm0 = ld(A.nbm, (uint32_t)xg + (uint32_t)A.nx * ((uint32_t)yg + (uint32_t)A.ny * z0));
   }
   if (SRC == PULL) {
+    // all loads of a thread before its LDS writes; one-step wraps on lattices
+    // at least a tile plus halo wide (block-uniform test), else modulo
     __syncthreads();
-    for (int k = tid; k < TS; k += 256) {
-      const int lx = k % PX, ly = (k / PX) % PY, lz = k / (PX * PY);
-      const int gxx = wrapi(x0 + lx - 1, A.nx);
-      const int gyy = wrapi(y0 + ly - 1, A.ny);
-      const int gzz = (D == 3) ? wrapi(z0 + lz - 1, A.nz) : 0;
-      const uint32_t g = (uint32_t)gxx + (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz);
-      ta[k] = ld(A.in.a, g);
-      tB[k] = ld(A.in.B, g);
-      tB[TS + k] = ld(A.in.B + A.N, g);
-      if (D == 3) tB[2 * TS + k] = ld(A.in.B + 2 * (size_t)A.N, g);
-    }
+    constexpr int IT = (TS + 255) / 256;
+    auto fill = [&](auto wrap) {
+      R va[IT];
+      float vb[IT][D];
+#pragma unroll
+      for (int m = 0; m < IT; ++m) {
+        const int k = tid + m * 256;
+        if (k < TS) {
+          const int lx = k % PX, ly = (k / PX) % PY, lz = k / (PX * PY);
+          const int gxx = wrap(x0 + lx - 1, A.nx);
+          const int gyy = wrap(y0 + ly - 1, A.ny);
+          const int gzz = (D == 3) ? wrap(z0 + lz - 1, A.nz) : 0;
+          const uint32_t g = (uint32_t)gxx + (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz);
+          va[m] = ld(A.in.a, g);
+#pragma unroll
+          for (int d = 0; d < D; ++d) vb[m][d] = ld(A.in.B + (size_t)d * A.N, g);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < IT; ++m) {
+        const int k = tid + m * 256;
+        if (k < TS) {
+          ta[k] = va[m];
+#pragma unroll
+          for (int d = 0; d < D; ++d) tB[d * TS + k] = vb[m][d];
+        }
+      }
+    };
+    if (A.nx >= PX - 1 && A.ny >= PY - 1 && (D == 2 || A.nz >= PZ - 1))
+      fill([](int v, int n) { return wrap_near(v, n); });
+    else
+      fill([](int v, int n) { return wrapi(v, n); });
     __syncthreads();
   }
   const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
@@ -473,16 +496,36 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
     if (xg < A.nx && yg < A.ny) gm0 = ld(A.nbm, (uint32_t)xg + (uint32_t)A.nx * ((uint32_t)yg + (uint32_t)A.ny * z0));
   }
 
-  // stage psi(tile + halo); wall rows read their fluid neighbour (copy rule)
+  // stage psi(tile + halo); wall rows read their fluid neighbour (copy rule).
+  // A thread issues all its loads before its LDS writes; on lattices at least
+  // a tile plus halo wide in every direction a coordinate wraps at most once
+  // (a block-uniform test picks the one-step wrap over integer modulo).
   __syncthreads();
-  for (int k = tid; k < LX * LY * LZ; k += NT) {
-    const int lx = k % LX, ly = (k / LX) % LY, lz = k / (LX * LY);
-    const int gxx = wrapi(x0 + lx - H, A.nx);
-    int gyy = y0 + ly - H;
-    if (A.walls) gyy = gyy < 1 ? 1 : (gyy > A.ny - 2 ? A.ny - 2 : gyy);
-    else gyy = wrapi(gyy, A.ny);
-    const int gzz = (D == 3) ? wrapi(z0 + lz - H, A.nz) : 0;
-    tile[k] = ld(A.psi, (uint32_t)gxx + (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz));
+  {
+    constexpr int FILL = LX * LY * LZ, IT = (FILL + NT - 1) / NT;
+    auto fill = [&](auto wrap) {
+      R v[IT];
+#pragma unroll
+      for (int m = 0; m < IT; ++m) {
+        const int k = tid + m * NT;
+        if (k < FILL) {
+          const int lx = k % LX, ly = (k / LX) % LY, lz = k / (LX * LY);
+          const int gxx = wrap(x0 + lx - H, A.nx);
+          int gyy = y0 + ly - H;
+          if (A.walls) gyy = gyy < 1 ? 1 : (gyy > A.ny - 2 ? A.ny - 2 : gyy);
+          else gyy = wrap(gyy, A.ny);
+          const int gzz = (D == 3) ? wrap(z0 + lz - H, A.nz) : 0;
+          v[m] = ld(A.psi, (uint32_t)gxx + (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz));
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < IT; ++m)
+        if (tid + m * NT < FILL) tile[tid + m * NT] = v[m];
+    };
+    if (A.nx >= LX - H && A.ny >= LY - H && (D == 2 || A.nz >= LZ - H))
+      fill([](int v, int n) { return wrap_near(v, n); });
+    else
+      fill([](int v, int n) { return wrapi(v, n); });
   }
   __syncthreads();
 
