@@ -50,7 +50,8 @@ int blocks_main(const lb_handle *h) {
 
 int blocks_phase(const lb_handle *h) {
   const lb_params &p = h->p;
-  const int gz = h->D == 3 ? (p.nz + TZP3 - 1) / TZP3 : 1;
+  const int tz = h->s_elem == 2 ? TZP3_16 : TZP3;
+  const int gz = h->D == 3 ? (p.nz + tz - 1) / tz : 1;
   return ((p.nx + 63) / 64) * ((p.ny + 3) / 4) * gz;
 }
 
@@ -81,7 +82,7 @@ void launch_main(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hip
 
 template <int D, typename S, typename R, int SRC>
 void launch_phase(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  launch(k_phase<D, S, R, SRC, (D == 3 ? TZP3 : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1)>, dim3(blocks_phase(h)),
+  launch(k_phase<D, S, R, SRC, (D == 3 ? tzp3<S>() : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1)>, dim3(blocks_phase(h)),
          dim3(64, 4), h->stream, e0, e1, a);
 }
 
