@@ -74,23 +74,24 @@ struct Img {
 // LDS buffers, the next step's global loads issued before the current step's
 // MFMAs (one barrier per step).  The problem supplies 8-element operand
 // chunks -- ROW: 8 consecutive k of one row; COL: 8 consecutive rows at one
-// k, gathered for 4 consecutive k and stored transposed into LDS as 8-byte
-// rows -- and consumes the accumulators in store().  K may be split over
+// k, gathered for COLV = 2 consecutive k and stored transposed into LDS as
+// 4-byte rows (two k per thread keep every thread gathering) -- and consumes
+// the accumulators in store().  K may be split over
 // gridDim.z (the problem decides each split's range).
 enum { ROW = 0, COL = 1 };
-typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+constexpr int COLV = 2;  // consecutive k per COL chunk
 
 template <int LAYOUT, int R>
 struct ChunkMap {
-  static constexpr int N = LAYOUT == ROW ? R * BK / 8 : R * BK / 32;  // chunks per tile
-  static constexpr int V = LAYOUT == ROW ? 1 : 4;                     // bf16x8 per chunk
+  static constexpr int N = LAYOUT == ROW ? R * BK / 8 : R * BK / (8 * COLV);  // chunks per tile
+  static constexpr int V = LAYOUT == ROW ? 1 : COLV;                          // bf16x8 per chunk
   __device__ __forceinline__ static void at(int q, int &row, int &k) {
     if (LAYOUT == ROW) {
       row = q >> 2;
       k = (q & 3) * 8;
     } else {
       row = (q % (R / 8)) * 8;
-      k = (q / (R / 8)) * 4;
+      k = (q / (R / 8)) * COLV;
     }
   }
 };
@@ -103,12 +104,11 @@ __device__ __forceinline__ void put_chunk(bf16 (*S)[LDK], int row, int k, const 
   } else {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      bf16x4 w;
-      w[0] = v[0][j];
-      w[1] = v[1][j];
-      w[2] = v[2][j];
-      w[3] = v[3][j];
-      *reinterpret_cast<bf16x4 *>(&S[row + j][k]) = w;
+      typedef __attribute__((ext_vector_type(COLV))) __bf16 bfv;
+      bfv w;
+#pragma unroll
+      for (int t = 0; t < COLV; ++t) w[t] = v[t][j];
+      *reinterpret_cast<bfv *>(&S[row + j][k]) = w;
     }
   }
 }
