@@ -30,7 +30,7 @@ int fail(int code, const char *fmt, ...);
 #define LBNCI_BY3 4
 #endif
 #ifndef LBNCI_TZ3
-#define LBNCI_TZ3 4
+#define LBNCI_TZ3 1
 #endif
 #ifndef LBNCI_H3
 #define LBNCI_H3 1

@@ -620,11 +620,11 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         if (A.walls && (yt <= 0 || yt >= A.ny - 1)) break;
         R pv;
         if constexpr (GEOM) {
-          // the probe stops at any node that is not fluid; the mask word and
-          // psi of the sample are loaded together.  LDS value read at clamped
-          // offsets, the global value only beyond the halo (keeps the two
-          // loads apart)
-          // (a geometry's extents exceed the probe reach: one wrap at most)
+          // the probe stops at any node that is not fluid; the sample's mask
+          // word and psi are loaded together (a geometry's extents exceed the
+          // probe reach, so one wrap step suffices).  psi: the LDS value read
+          // at clamped offsets, the global value only beyond the halo (keeps
+          // the two loads apart)
           const int xt = wrap_near(x + ox, A.nx);
           const int zt = (D == 3) ? wrap_near(z + oz, A.nz) : 0;
           const uint32_t ns =
