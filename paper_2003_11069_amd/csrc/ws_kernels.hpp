@@ -602,30 +602,44 @@ static __global__ __launch_bounds__(256) void k_adam(float *w, const float *g, f
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// BF16 weight copies of a KSxKS convolution: Wt[co][k] = W[co][k] and the
-// flipped transpose WtT[ci][(ky*KS+kx)*Cout + co] = W[co][((KS-1-ky)*KS+KS-1-kx)*Cin + ci].
-static __global__ __launch_bounds__(256) void k_conv_weights(const float *W, int Cout, int Cin, int KS, bf16 *Wt,
-                                                      bf16 *WtT) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int K = KS * KS * Cin;
-  if (i >= Cout * K) return;
-  const int co = i / K, k = i - co * K, tap = k / Cin, ci = k - tap * Cin;
-  const int ky = tap / KS, kx = tap % KS;
-  const bf16 v = (bf16)W[i];
-  Wt[i] = v;
-  const int ftap = (KS - 1 - ky) * KS + (KS - 1 - kx);
-  if (WtT) WtT[(size_t)ci * KS * KS * Cout + ftap * Cout + co] = v;
+// All layers' BF16 weight copies in one launch (the table travels in the
+// kernel argument; layer l owns the blocks from blk0).  A KSxKS convolution
+// W[co][k]: Wt = W and the flipped transpose
+// WtT[ci][(ky*KS+kx)*Cout + co] = W[co][((KS-1-ky)*KS+KS-1-kx)*Cin + ci];
+// an up-sampling W[d][co][ci] (up = 1): Wt = W, WtT[ci][d*Cout + co].
+struct WLayer {
+  const float *W;
+  bf16 *Wt, *WtT;
+  int Cout, Cin, KS, up, blk0;
+};
+constexpr int MAX_WLAYERS = 32;
+struct WTable {
+  WLayer l[MAX_WLAYERS];
+  int n;
+};
+static __global__ __launch_bounds__(256) void k_refresh_weights(WTable t) {
+  int li = 0;
+  while (li + 1 < t.n && (int)blockIdx.x >= t.l[li + 1].blk0) ++li;  // block-uniform
+  const WLayer &L = t.l[li];
+  const int i = ((int)blockIdx.x - L.blk0) * 256 + threadIdx.x;
+  if (L.up) {
+    if (i >= 4 * L.Cout * L.Cin) return;
+    const int ci = i % L.Cin, q = i / L.Cin, co = q % L.Cout, d = q / L.Cout;
+    const bf16 v = (bf16)L.W[i];
+    L.Wt[i] = v;
+    L.WtT[(size_t)ci * 4 * L.Cout + d * L.Cout + co] = v;
+  } else {
+    const int K = L.KS * L.KS * L.Cin;
+    if (i >= L.Cout * K) return;
+    const int co = i / K, k = i - co * K, tap = k / L.Cin, ci = k - tap * L.Cin;
+    const int ky = tap / L.KS, kx = tap % L.KS;
+    const bf16 v = (bf16)L.W[i];
+    L.Wt[i] = v;
+    const int ftap = (L.KS - 1 - ky) * L.KS + (L.KS - 1 - kx);
+    if (L.WtT) L.WtT[(size_t)ci * L.KS * L.KS * L.Cout + ftap * L.Cout + co] = v;
+  }
 }
 
-// BF16 copies of an up-sampling weight W[d][co][ci]: Wt = W, WtT[ci][d*Cout + co].
-static __global__ __launch_bounds__(256) void k_up_weights(const float *W, int Cout, int Cin, bf16 *Wt, bf16 *WtT) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 4 * Cout * Cin) return;
-  const int ci = i % Cin, t = i / Cin, co = t % Cout, d = t / Cout;
-  const bf16 v = (bf16)W[i];
-  Wt[i] = v;
-  WtT[(size_t)ci * 4 * Cout + d * Cout + co] = v;
-}
 
 static __global__ __launch_bounds__(256) void k_fill_f32(float *p, int64_t n, float v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -149,19 +149,24 @@ Up make_up(int64_t &off, int Cin, int Cout) {
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// BF16 weight copies of every layer from the FP32 master weights, one launch
 int refresh_weights(ws_net *n) {
-  auto conv = [&](Conv &c) {
-    hipLaunchKernelGGL(k_conv_weights, dim3(blocks(c.nw())), dim3(256), 0, n->stream, n->params + c.w_off, c.Cout,
-                       c.Cin, c.KS, c.Wt, c.WtT);
+  WTable t{};
+  int blk = 0;
+  auto add = [&](const float *W, bf16 *Wt, bf16 *WtT, int Cout, int Cin, int KS, int up, int64_t nw) {
+    if (t.n == MAX_WLAYERS) return;  // not reached: 6 levels make 28 layers
+    t.l[t.n] = WLayer{W, Wt, WtT, Cout, Cin, KS, up, blk};
+    ++t.n;
+    blk += (int)blocks(nw);
   };
+  auto conv = [&](Conv &c) { add(n->params + c.w_off, c.Wt, c.WtT, c.Cout, c.Cin, c.KS, 0, c.nw()); };
   for (auto &c : n->e1) conv(c);
   for (auto &c : n->e2) conv(c);
   for (auto &c : n->d1) conv(c);
   for (auto &c : n->d2) conv(c);
   conv(n->head);
-  for (auto &u : n->up)
-    hipLaunchKernelGGL(k_up_weights, dim3(blocks(u.nw())), dim3(256), 0, n->stream, n->params + u.w_off, u.Cout,
-                       u.Cin, u.Wt, u.WtT);
+  for (auto &u : n->up) add(n->params + u.w_off, u.Wt, u.WtT, u.Cout, u.Cin, 2, 1, u.nw());
+  hipLaunchKernelGGL(k_refresh_weights, dim3((unsigned)blk), dim3(256), 0, n->stream, t);
   HTRY(hipGetLastError());
   return WS_OK;
 }
