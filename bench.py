@@ -28,7 +28,13 @@ METRIC = "MLUPS/GPU + HBM roofline %; steps-to-steady-state plain vs learned war
 HBM_PEAK_GBPS = 8000.0
 # bytes of the paper's two-population state read + written once per fluid
 # node-update plus psi written and read once (FP32 populations)
-B_ALG_TWO_POP = {2: 2 * 2 * 9 * 4 + 8, 3: 2 * 2 * 27 * 4 + 8}
+def two_pop_bytes(dim: int, storage: str) -> int:
+    """The paper's own state per fluid-node update: both components'
+    populations read and written once in the storage precision, plus psi
+    written and read once (4 B each)."""
+    q = 9 if dim == 2 else 27
+    e = 2 if storage in ("fp16", "bf16") else 4
+    return 2 * 2 * q * e + 8
 
 
 def main_kernel_bytes(dim: int, storage: str) -> int:
@@ -155,8 +161,8 @@ def main(argv=None):
                      "avg_ms": round(ms_main, 5), "launches": kt["launches"]},
         "step": {"k_phase_avg_ms": round(ms_phase, 5), "k_main_avg_ms": round(ms_main, 5),
                  "graphs": L.graphs,
-                 "effective_GBps_two_pop_state": round(B_ALG_TWO_POP[dim] * mlups * 1e6 / 1e9, 1),
-                 "effective_frac_two_pop_state": round(B_ALG_TWO_POP[dim] * mlups * 1e6 / 1e9
+                 "effective_GBps_two_pop_state": round(two_pop_bytes(dim, a.storage) * mlups * 1e6 / 1e9, 1),
+                 "effective_frac_two_pop_state": round(two_pop_bytes(dim, a.storage) * mlups * 1e6 / 1e9
                                                        / HBM_PEAK_GBPS, 4)},
         "copy_probe": {"GBps": round(cp["GBps"], 1), "frac_of_peak": round(cp["GBps"] / HBM_PEAK_GBPS, 4),
                        "k_main_frac_of_copy": round(achieved / cp["GBps"], 4)},
