@@ -1,0 +1,49 @@
+"""GPU parity at lattice sizes around the LDS tile thresholds.
+
+The kernels fill their LDS tiles (k_main: psi with its halo; k_phase: the
+colour scalars with a one-node halo) wrapping each coordinate by one
+conditional step when the lattice is at least a tile plus its halo wide in
+every direction, and by integer modulo otherwise.  At the threshold a halo
+coordinate wraps by the largest amount.  The one-step bounds: D3Q27 k_main
+(64 x 4 x 1 tiles, halo 1) nx >= 65, ny >= 5, nz >= 2; k_phase (64 x 4 tiles,
+2 planes with FP32 storage, 4 with 16-bit storage) nx >= 65, ny >= 5, nz >= 3
+(FP32) or 5 (16-bit); D2Q9 k_main (halo 4) nx >= 68, ny >= 8 and k_phase
+nx >= 65, ny >= 5.  Each case below sits on or one node below a bound and
+runs against the FP64 oracle with NCI active, periodic or with walls.
+"""
+import pytest
+
+import synth
+from gpu_common import say, make_pair, fluid_mask, field_errors
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 100
+# storage -> (rho bound, u bound): FP32 the parity bar, FP16 the stated budget
+BOUNDS = {"fp32": (1e-5, 1e-5), "fp16": (2e-3, 0.2)}
+
+CASES = [
+    # (lattice, nx, ny, nz, walls, storage)
+    (1, 65, 5, 3, 0, "fp32"),   # both kernels one-step, at the bound
+    (1, 64, 5, 3, 0, "fp32"),   # both below in x: modulo
+    (1, 65, 5, 2, 0, "fp32"),   # k_main one-step, k_phase modulo (nz < 3)
+    (1, 65, 7, 3, 1, "fp32"),   # walls: y clamped, x and z one-step
+    (1, 65, 5, 5, 0, "fp16"),   # 16-bit k_phase (4 planes) at its bound
+    (1, 65, 5, 4, 0, "fp16"),   # 16-bit k_phase below: modulo
+    (0, 68, 8, 1, 0, "fp32"),   # D2Q9 k_main at its bound
+    (0, 67, 8, 1, 0, "fp32"),   # D2Q9 k_main below
+]
+
+
+@pytest.mark.parametrize("lat,nx,ny,nz,walls,storage", CASES)
+def test_parity_at_tile_thresholds(lat, nx, ny, nz, walls, storage):
+    p = synth.base_params(lattice=lat, nx=nx, ny=ny, nz=nz, walls_y=walls, A_nci=0.01, h_min=1.0, h_max=2.0)
+    case = synth.random_fields(p, seed=nx + 7 * ny + 31 * nz)
+    say(f"[gpu] lattice {'D3Q27' if lat else 'D2Q9'} {nx}x{ny}x{nz} walls {walls} {storage}, {STEPS} steps")
+    o, g = make_pair(case, storage=storage)
+    o.step(STEPS)
+    g.step(STEPS)
+    e = field_errors(o, g, fluid_mask(case.params, case.N))
+    say(f"  errors {e}")
+    tr, tu = BOUNDS[storage]
+    assert e["rho1"] <= tr and e["rho2"] <= tr and e["u"] <= tu
