@@ -52,7 +52,8 @@ int blocks_phase(const lb_handle *h) {
   const lb_params &p = h->p;
   const int tz = h->s_elem == 2 ? TZP3_16 : TZP3;
   const int gz = h->D == 3 ? (p.nz + tz - 1) / tz : 1;
-  return ((p.nx + 63) / 64) * ((p.ny + 3) / 4) * gz;
+  const int by = h->D == 3 ? PBY3 : 4;
+  return ((p.nx + 63) / 64) * ((p.ny + by - 1) / by) * gz;
 }
 
 
@@ -82,8 +83,8 @@ void launch_main(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hip
 
 template <int D, typename S, typename R, int SRC>
 void launch_phase(lb_handle *h, const Args<S, R> &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  launch(k_phase<D, S, R, SRC, (D == 3 ? tzp3<S>() : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1)>, dim3(blocks_phase(h)),
-         dim3(64, 4), h->stream, e0, e1, a);
+  launch(k_phase<D, S, R, SRC, (D == 3 ? tzp3<S>() : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1), 0, (D == 3 ? PBY3 : 4)>,
+         dim3(blocks_phase(h)), dim3(64, D == 3 ? PBY3 : 4), h->stream, e0, e1, a);
 }
 
 // One pass over the lattice in the given mode; STEP modes write the other copy.

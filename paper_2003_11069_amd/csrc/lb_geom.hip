@@ -130,8 +130,8 @@ void launch_main_geom(lb_handle *h, const Args<S, R> &a, hipEvent_t e0, hipEvent
 
 template <int D, typename S, typename R, int SRC>
 void launch_phase_geom(lb_handle *h, const Args<S, R> &a, hipEvent_t e0, hipEvent_t e1) {
-  launch(k_phase<D, S, R, SRC, (D == 3 ? tzp3<S>() : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1), 1>, dim3(blocks_phase(h)),
-         dim3(64, 4), h->stream, e0, e1, a);
+  launch(k_phase<D, S, R, SRC, (D == 3 ? tzp3<S>() : 1), (D == 3 ? LBNCI_WPE_PHASE3 : 1), 1, (D == 3 ? PBY3 : 4)>,
+         dim3(blocks_phase(h)), dim3(64, D == 3 ? PBY3 : 4), h->stream, e0, e1, a);
 }
 
 template <int D, typename S, typename R, int SRC>

@@ -41,6 +41,9 @@ int fail(int code, const char *fmt, ...);
 #ifndef LBNCI_TZP3_16
 #define LBNCI_TZP3_16 4
 #endif
+#ifndef LBNCI_PBY3
+#define LBNCI_PBY3 8
+#endif
 #ifndef LBNCI_WPE_MAIN3
 #define LBNCI_WPE_MAIN3 1
 #endif
@@ -51,6 +54,7 @@ constexpr int BY2 = LBNCI_BY2, TZ2 = 1, H2 = 4;  // D2Q9: halo 4, NCI probe from
 constexpr int BY3 = LBNCI_BY3, TZ3 = LBNCI_TZ3, H3 = LBNCI_H3;  // D3Q27: probe beyond the halo from L2
 constexpr int TZP3 = LBNCI_TZP3;                 // k_phase z-planes per block (3-D)
 constexpr int TZP3_16 = LBNCI_TZP3_16;           // the same with 16-bit storage (measured faster)
+constexpr int PBY3 = LBNCI_PBY3;                 // rows per single-lattice k_phase block (3-D)
 // z-planes per single-lattice k_phase block for storage type S
 template <typename S>
 constexpr int tzp3() { return sizeof(S) == 2 ? TZP3_16 : TZP3; }

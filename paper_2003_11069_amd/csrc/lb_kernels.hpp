@@ -318,18 +318,20 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
 // scalars are staged in LDS with a one-node halo (each is read by up to Q
 // neighbours).  Safe to call repeatedly from one block (persistent kernels):
 // it synchronises before reusing the LDS tile and never returns early.
-template <int D, int TZP>
+template <int D, int TZP, int PBY = 4>
 struct PhaseTile {
-  static constexpr int PX = 66, PY = 6, PZ = (D == 3) ? TZP + 2 : 1;
+  static constexpr int PX = 66, PY = PBY + 2, PZ = (D == 3) ? TZP + 2 : 1;
   static constexpr int TS = PX * PY * PZ;
 };
 
-template <int D, typename S, typename R, int SRC, int TZP, int GEOM = 0>
+template <int D, typename S, typename R, int SRC, int TZP, int GEOM = 0, int PBY = 4>
 __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, int bz, R *ta,
                                            float *tB) {
-  constexpr int PX = PhaseTile<D, TZP>::PX, PY = PhaseTile<D, TZP>::PY, PZ = PhaseTile<D, TZP>::PZ;
-  constexpr int TS = PhaseTile<D, TZP>::TS;
-  const int x0 = bx * 64, y0 = by * 4, z0 = (D == 3) ? bz * TZP : 0;
+  using PT = PhaseTile<D, TZP, PBY>;
+  constexpr int PX = PT::PX, PY = PT::PY, PZ = PT::PZ;
+  constexpr int TS = PT::TS;
+  constexpr int NT = 64 * PBY;  // threads per block (64 x PBY)
+  const int x0 = bx * 64, y0 = by * PBY, z0 = (D == 3) ? bz * TZP : 0;
   const int tid = threadIdx.x + 64 * threadIdx.y;
   // geometry: the first node's mask word is loaded before the LDS fill, so
   // its non-fluid test below waits for nothing (geometries have no wall rows)
@@ -342,13 +344,13 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
     // all loads of a thread before its LDS writes; one-step wraps on lattices
     // at least a tile plus halo wide (block-uniform test), else modulo
     __syncthreads();
-    constexpr int IT = (TS + 255) / 256;
+    constexpr int IT = (TS + NT - 1) / NT;
     auto fill = [&](auto wrap) {
       R va[IT];
       float vb[IT][D];
 #pragma unroll
       for (int m = 0; m < IT; ++m) {
-        const int k = tid + m * 256;
+        const int k = tid + m * NT;
         if (k < TS) {
           const int lx = k % PX, ly = (k / PX) % PY, lz = k / (PX * PY);
           const int gxx = wrap(x0 + lx - 1, A.nx);
@@ -362,7 +364,7 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
       }
 #pragma unroll
       for (int m = 0; m < IT; ++m) {
-        const int k = tid + m * 256;
+        const int k = tid + m * NT;
         if (k < TS) {
           ta[k] = va[m];
 #pragma unroll
@@ -400,29 +402,29 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
 }
 
 // Number of phase tiles of a lattice.
-template <int D, int TZP>
+template <int D, int TZP, int PBY = 4>
 __host__ __device__ __forceinline__ int phase_tiles(int nx, int ny, int nz) {
-  return ((nx + 63) / 64) * ((ny + 3) / 4) * ((D == 3) ? (nz + TZP - 1) / TZP : 1);
+  return ((nx + 63) / 64) * ((ny + PBY - 1) / PBY) * ((D == 3) ? (nz + TZP - 1) / TZP : 1);
 }
 
-template <int D, int TZP>
+template <int D, int TZP, int PBY = 4>
 __device__ __forceinline__ void phase_decode(int nx, int ny, int lb, int &bx, int &by, int &bz) {
-  const int gx = (nx + 63) / 64, gy = (ny + 3) / 4;
+  const int gx = (nx + 63) / 64, gy = (ny + PBY - 1) / PBY;
   bx = lb % gx;
   by = (lb / gx) % gy;
   bz = lb / (gx * gy);
 }
 
 // k_phase: one phase tile per block over a single lattice.
-template <int D, typename S, typename R, int SRC, int TZP, int WPE = 1, int GEOM = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_phase(Args<S, R> A) {
-  constexpr int TS = PhaseTile<D, TZP>::TS;
+template <int D, typename S, typename R, int SRC, int TZP, int WPE = 1, int GEOM = 0, int PBY = 4>
+__global__ __launch_bounds__(64 * PBY) __attribute__((amdgpu_waves_per_eu(WPE))) void k_phase(Args<S, R> A) {
+  constexpr int TS = PhaseTile<D, TZP, PBY>::TS;
   constexpr bool STAGE = (SRC == PULL);
   __shared__ R ta[STAGE ? TS : 1];
   __shared__ float tB[STAGE ? D * TS : 1];
   int bx, by, bz;
-  phase_decode<D, TZP>(A.nx, A.ny, logical_block(blockIdx.x, gridDim.x, A.xcd_remap), bx, by, bz);
-  phase_tile<D, S, R, SRC, TZP, GEOM>(A, bx, by, bz, ta, tB);
+  phase_decode<D, TZP, PBY>(A.nx, A.ny, logical_block(blockIdx.x, gridDim.x, A.xcd_remap), bx, by, bz);
+  phase_tile<D, S, R, SRC, TZP, GEOM, PBY>(A, bx, by, bz, ta, tB);
 }
 
 // A_h: A below h_min, A (h_min/h)^3 up to h_max, 0 beyond (Eq. near_c text).
