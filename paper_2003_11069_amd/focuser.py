@@ -107,28 +107,30 @@ def sweep(phis, scale=2.0, u_c=0.004, A_s=0.1, N_c=0.1, W_out=64, steps=60000, t
           storage="fp32", keep_samples=False):
     """``run`` for every flow ratio in ``phis`` at once: one handle per phi,
     each on its own HIP stream (default priority), stepped in lockstep.  One
-    focuser of this size fills well under one wave per SIMD, so the handles'
+    focuser of this size keeps under one wave per SIMD busy, so the handles'
     kernels run side by side on the idle compute units; each handle's
     arithmetic is that of ``run`` (the same results, bit for bit).  Returns
     one result per phi, each with the wall time of the whole sweep."""
-    streams = [_lb.Stream() for _ in phis]
-    runs = [_Run(scale, phi, u_c, A_s, N_c, W_out, storage, stream=st.handle)
-            for phi, st in zip(phis, streams)]
-    t0 = time.perf_counter()
-    for r in runs:
-        r.lat.step(t_skip)
-    while runs[0].lat.t < steps:
-        for r in runs:          # enqueue every handle's steps before the first sample waits
-            r.lat.step(every)
+    streams, runs = [], []
+    try:
+        for phi in phis:
+            streams.append(_lb.Stream())
+            runs.append(_Run(scale, phi, u_c, A_s, N_c, W_out, storage, stream=streams[-1].handle))
+        t0 = time.perf_counter()
         for r in runs:
-            r.sample()
-    elapsed = time.perf_counter() - t0
-    out = [r.result(steps, t_skip, every, elapsed, keep_samples) for r in runs]
-    for r in runs:
-        r.lat.close()
-    for st in streams:
-        st.close()
-    return out
+            r.lat.step(t_skip)
+        while runs[0].lat.t < steps:
+            for r in runs:          # enqueue every handle's steps before the first sample waits
+                r.lat.step(every)
+            for r in runs:
+                r.sample()
+        elapsed = time.perf_counter() - t0
+        return [r.result(steps, t_skip, every, elapsed, keep_samples) for r in runs]
+    finally:  # handles before the streams they use
+        for r in runs:
+            r.lat.close()
+        for st in streams:
+            st.close()
 
 
 def main(argv=None):
