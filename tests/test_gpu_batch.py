@@ -201,3 +201,19 @@ def test_batch_3d_channel_against_oracle():
         eu = np.abs(ug - uo)[:, m].max() / np.abs(uo[:, m]).max()
         say(f"  channel {k}: rho1 {e1:.2e} rho2 {e2:.2e} u {eu:.2e}")
         assert e1 <= 1e-5 and e2 <= 1e-5 and eu <= 1e-5
+
+
+@pytest.mark.parametrize("mode", [P.LB_BATCH_LAUNCH, P.LB_BATCH_PERSISTENT])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_fp16_matches_single_lattices(mode, dim):
+    """FP16 deviation storage: batched channels equal single lattices."""
+    cases = CASES[:3] if dim == 2 else CASES_3D
+    say(f"[gpu] FP16 batch vs single, {dim}-D, mode {mode}")
+    b, ps = _batch(cases, storage=P.STORAGE["fp16"])
+    b.step(29, mode)
+    for k, c in enumerate(cases):
+        g = P.Lattice(ps[k])
+        g.init_fields(c.rho1, c.rho2)
+        g.step(29)
+        for x, y in zip(b.fields(k), g.fields()):
+            assert np.array_equal(x, y), f"channel {k}"
