@@ -205,11 +205,12 @@ def test_batch_3d_channel_against_oracle():
 
 @pytest.mark.parametrize("mode", [P.LB_BATCH_LAUNCH, P.LB_BATCH_PERSISTENT])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_batch_fp16_matches_single_lattices(mode, dim):
-    """FP16 deviation storage: batched channels equal single lattices."""
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_batch_16bit_matches_single_lattices(storage, dim, mode):
+    """16-bit deviation storage: batched channels equal single lattices."""
     cases = CASES[:3] if dim == 2 else CASES_3D
-    say(f"[gpu] FP16 batch vs single, {dim}-D, mode {mode}")
-    b, ps = _batch(cases, storage=P.STORAGE["fp16"])
+    say(f"[gpu] {storage} batch vs single, {dim}-D, mode {mode}")
+    b, ps = _batch(cases, storage=P.STORAGE[storage])
     b.step(29, mode)
     for k, c in enumerate(cases):
         g = P.Lattice(ps[k])
