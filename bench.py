@@ -96,7 +96,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep", "unet", "analysis", "geometry",
                                                           "focuser"])
     ap.add_argument("--batch", type=int, default=16, help="U-Net training batch (--workload unet)")
-    ap.add_argument("--mode", default="persistent", choices=["persistent", "launch"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "persistent", "launch"],
+                    help="batched sweep: the autotuner's choice, or a fixed mode")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -177,7 +178,9 @@ def main(argv=None):
 def bench_sweep(a):
     """Batched sweep: 64 wall-bounded D2Q9 channels of uneven size (Lx 256..1024,
     Ly 64..160, hexagonal droplet packings, pressure gradient 1e-6..1e-4, NCI
-    strength 0..0.05), stepped together in one persistent launch (or per-step
+    strength 0..0.05), stepped together in the mode and tile height the
+    library's autotuner picks (its trial steps are real steps, taken before
+    the timed region), or in a fixed mode (one persistent launch, or per-step
     batched launches).  Prints one JSON line (aggregate MLUPS over fluid
     nodes)."""
     import synth
@@ -188,7 +191,12 @@ def bench_sweep(a):
     b = P.Batch(ps)
     for k, c in enumerate(cases):
         b.init_fields(k, c.rho1, c.rho2)
-    mode = P.LB_BATCH_PERSISTENT if a.mode == "persistent" else P.LB_BATCH_LAUNCH
+    tuned = None
+    if a.mode == "auto":
+        tuned = b.tune(trial_steps=20)
+        mode = P.LB_BATCH_AUTO
+    else:
+        mode = P.LB_BATCH_PERSISTENT if a.mode == "persistent" else P.LB_BATCH_LAUNCH
     fluid = sum(p.nx * (p.ny - 2) for p in ps)
     b.step(a.warmup, mode)
     t0 = time.perf_counter()
@@ -204,7 +212,7 @@ def bench_sweep(a):
            "data": "synthetic (seeded channel sweep)",
            "config": {"workload": "64 D2Q9 channels, Lx 256..1024, Ly 64..160, seeded sweep",
                       "channels": len(ps), "fluid_nodes": fluid, "storage": a.storage, "mode": a.mode,
-                      "graphs": b.graphs},
+                      "tuned": tuned, "graphs": b.graphs},
            "step_bytes_per_node_measured_layout": bytes_node,
            "achieved_GBps_step": round(bytes_node * mlups * 1e6 / 1e9, 1)}
     print(json.dumps(out), flush=True)
