@@ -70,7 +70,8 @@ struct Img {
 // ---------------------------------------------------------------------------
 // GEMM engine: C[M,N] = sum_k A[m,k] B[k,n] on v_mfma_f32_16x16x32_bf16.
 // Block tile BM x BN (BM in {64,128}, BN in {32,64,128}), 4 waves in 2 x 2,
-// each (BM/2) x (BN/2) of 16 x 16 MFMA tiles; K in steps of 32 through two
+// each (BM/2) x (BN/2) of 16 x 16 MFMA tiles; K in steps of KB (32 or 64,
+// one or two MFMA slices) through two
 // LDS buffers, the next step's global loads issued before the current step's
 // MFMAs (one barrier per step).  The problem supplies 8-element operand
 // chunks -- ROW: 8 consecutive k of one row; COL: 8 consecutive rows at one
@@ -81,14 +82,14 @@ struct Img {
 enum { ROW = 0, COL = 1 };
 constexpr int COLV = 2;  // consecutive k per COL chunk
 
-template <int LAYOUT, int R>
+template <int LAYOUT, int R, int KB = BK>
 struct ChunkMap {
-  static constexpr int N = LAYOUT == ROW ? R * BK / 8 : R * BK / (8 * COLV);  // chunks per tile
+  static constexpr int N = LAYOUT == ROW ? R * KB / 8 : R * KB / (8 * COLV);  // chunks per tile
   static constexpr int V = LAYOUT == ROW ? 1 : COLV;                          // bf16x8 per chunk
   __device__ __forceinline__ static void at(int q, int &row, int &k) {
     if (LAYOUT == ROW) {
-      row = q >> 2;
-      k = (q & 3) * 8;
+      row = q / (KB / 8);
+      k = (q % (KB / 8)) * 8;
     } else {
       row = (q % (R / 8)) * 8;
       k = (q / (R / 8)) * COLV;
@@ -97,8 +98,8 @@ struct ChunkMap {
 };
 
 // Stores one chunk (V vectors starting at v) into an LDS tile.
-template <int LAYOUT>
-__device__ __forceinline__ void put_chunk(bf16 (*S)[LDK], int row, int k, const bf16x8 *v) {
+template <int LAYOUT, int LD = LDK>
+__device__ __forceinline__ void put_chunk(bf16 (*S)[LD], int row, int k, const bf16x8 *v) {
   if (LAYOUT == ROW) {
     *reinterpret_cast<bf16x8 *>(&S[row][k]) = v[0];
   } else {
@@ -113,14 +114,15 @@ __device__ __forceinline__ void put_chunk(bf16 (*S)[LDK], int row, int k, const 
   }
 }
 
-template <class P, int BM_, int BN_>
+template <class P, int BM_, int BN_, int KB = BK>
 __global__ __launch_bounds__(256) void k_gemm(P prob) {
   constexpr int WM = BM_ / 2, WN = BN_ / 2, TM = WM / 16, TN = WN / 16;
-  using MA = ChunkMap<P::A_LAYOUT, BM_>;
-  using MB = ChunkMap<P::B_LAYOUT, BN_>;
+  constexpr int LD = KB + 8;  // LDS row stride (bf16)
+  using MA = ChunkMap<P::A_LAYOUT, BM_, KB>;
+  using MB = ChunkMap<P::B_LAYOUT, BN_, KB>;
   constexpr int CA = (MA::N + 255) / 256, CB = (MB::N + 255) / 256;
-  __shared__ __attribute__((aligned(16))) bf16 As[2][BM_][LDK];
-  __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN_][LDK];
+  __shared__ __attribute__((aligned(16))) bf16 As[2][BM_][LD];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN_][LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM_, n0 = blockIdx.y * BN_;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
@@ -161,14 +163,14 @@ __global__ __launch_bounds__(256) void k_gemm(P prob) {
       const int q = tid + 256 * c;
       int row, k;
       MA::at(q, row, k);
-      if (q < MA::N) put_chunk<P::A_LAYOUT>(As[buf], row, k, &ra[c * VA]);
+      if (q < MA::N) put_chunk<P::A_LAYOUT, LD>(As[buf], row, k, &ra[c * VA]);
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       const int q = tid + 256 * c;
       int row, k;
       MB::at(q, row, k);
-      if (q < MB::N) put_chunk<P::B_LAYOUT>(Bs[buf], row, k, &rb[c * VB]);
+      if (q < MB::N) put_chunk<P::B_LAYOUT, LD>(Bs[buf], row, k, &rb[c * VB]);
     }
   };
   if (kbeg < kend) {
@@ -178,18 +180,22 @@ __global__ __launch_bounds__(256) void k_gemm(P prob) {
   __syncthreads();
   int buf = 0;
   const int r = lane & 15, kq = 8 * (lane >> 4);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) load(k0 + BK);
-    bf16x8 a[TM], b[TN];
+  for (int k0 = kbeg; k0 < kend; k0 += KB) {
+    const bool more = k0 + KB < kend;
+    if (more) load(k0 + KB);
 #pragma unroll
-    for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][wm + 16 * i + r][kq]);
+    for (int ks = 0; ks < KB; ks += 32) {  // 32-deep MFMA slices of the LDS stage
+      bf16x8 a[TM], b[TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn + 16 * j + r][kq]);
+      for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][wm + 16 * i + r][ks + kq]);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn + 16 * j + r][ks + kq]);
 #pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;

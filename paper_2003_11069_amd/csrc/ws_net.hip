@@ -189,10 +189,29 @@ Tile pick_tile(int M, int N, int row_group) {
 // Tile of a split weight-gradient GEMM (small M, wide N; splits fill the chip).
 Tile pick_tile_split(int M, int N) { return Tile{M <= 64 ? 64 : 128, N <= 32 ? 32 : (N <= 64 ? 64 : 128)}; }
 
+// Tiles that run 64-deep K steps (two MFMA slices per LDS stage, twice the
+// work per global-load wait): measured faster only for the 3x3 data gradient
+// at 128 x 32 (105 -> 87 us at level 0) and the 3x3 forward at 64 x 128
+// (44 -> 38 us); elsewhere the larger LDS stage costs more occupancy than it
+// saves.  Split-K problems keep 32 (their chunks are multiples of 32).
+template <class P>
+struct DeepK {
+  static constexpr int bm = 0, bn = 0;
+};
+template <bool RELU>
+struct DeepK<ConvBwdData<3, RELU>> {
+  static constexpr int bm = 128, bn = 32;
+};
+template <bool RELU, bool F32>
+struct DeepK<ConvFwd<3, RELU, F32>> {
+  static constexpr int bm = 64, bn = 128;
+};
+
 template <class Prob, int BMt, int BNt>
 void launch(ws_net *n, const Prob &p, int M, int N, int splits) {
+  constexpr int KB = (BMt == DeepK<Prob>::bm && BNt == DeepK<Prob>::bn) ? 64 : BK;
   dim3 grid((M + BMt - 1) / BMt, (N + BNt - 1) / BNt, splits);
-  hipLaunchKernelGGL((k_gemm<Prob, BMt, BNt>), grid, dim3(256), 0, n->stream, p);
+  hipLaunchKernelGGL((k_gemm<Prob, BMt, BNt, KB>), grid, dim3(256), 0, n->stream, p);
 }
 
 template <class Prob>
