@@ -82,7 +82,20 @@ def cpu_baseline(case, budget_s: float):
     fluid = case.params["nx"] * (case.params["ny"] - 2 * case.params["walls_y"]) * case.params["nz"]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": fluid * n / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{n} steps of the same workload after 1 warm-up step, {el:.1f} s"}
+            "sample": f"{n} steps of the same workload after 1 warm-up step, {el:.1f} s",
+            "cpu": host_cpu_model()}
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main(argv=None):
