@@ -18,7 +18,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liblbo.so")
+# LBO_LIB points the tests' mutation checks at a deliberately altered build
+_LIB_PATH = os.environ.get("LBO_LIB") or os.path.join(_HERE, "liblbo.so")
 _lib = None
 
 D2Q9, D3Q27 = 0, 1

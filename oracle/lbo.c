@@ -38,9 +38,15 @@
  * Parity pins: tests/test_oracle_units.py and tests/test_oracle_physics.py.
  */
 #include "lbo.h"
+
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* lattices smaller than this run on one thread: nodes are independent, so the
+ * thread count never changes a result, and on small lattices the per-loop
+ * synchronisation of a thread team costs more than the work */
+#define LBO_PAR_MIN 16384
 
 #define QMAX 27
 
@@ -465,7 +471,7 @@ void lbo_get_populations(const lbo *h, double *f1, double *f2) {
 /* steps 1-2: psi on fluid nodes, then wall rows copied from their neighbour */
 static void compute_psi(lbo *h) {
   const lbo_params *p = &h->p;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->N >= LBO_PAR_MIN)
   for (int64_t n = 0; n < h->N; ++n) {
     if (!is_fluid(h, n)) continue;
     double r1 = 0, r2 = 0;
@@ -521,7 +527,7 @@ static void step_once(lbo *h) {
   const int64_t N = h->N;
   compute_psi(h);
   /* steps 3-8: collision at every fluid node into g1/g2 */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->N >= LBO_PAR_MIN)
   for (int64_t n = 0; n < N; ++n) {
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
     if (!is_fluid(h, n)) continue;
@@ -573,7 +579,7 @@ static void step_once(lbo *h) {
     }
   }
   /* step 9: pull streaming, half-way bounce-back from wall rows */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->N >= LBO_PAR_MIN)
   for (int64_t n = 0; n < N; ++n) {
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
     if (!is_fluid(h, n)) continue;
@@ -624,7 +630,7 @@ static void node_moments(lbo *h, int64_t n, double *r1, double *r2, double j[3])
 void lbo_fields(lbo *h, double *rho1, double *rho2, double *u) {
   const lbo_params *p = &h->p;
   compute_psi(h);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->N >= LBO_PAR_MIN)
   for (int64_t n = 0; n < h->N; ++n) {
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
     if (!is_fluid(h, n)) {
@@ -674,7 +680,7 @@ void lbo_diagnostics(lbo *h, double *psi, double *G, double *Frep, int32_t *hit,
   const lbo_params *p = &h->p;
   compute_psi(h);
   memcpy(psi, h->psi, sizeof(double) * (size_t)h->N);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->N >= LBO_PAR_MIN)
   for (int64_t n = 0; n < h->N; ++n) {
     int x = (int)(n % p->nx), y = (int)((n / p->nx) % p->ny), z = (int)(n / ((int64_t)p->nx * p->ny));
     double g[3] = {0, 0, 0}, F[3], fr[3] = {0, 0, 0}, mg = INFINITY;
