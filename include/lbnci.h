@@ -111,6 +111,14 @@ typedef struct {
                           variant); alpha_2 = 1 - gamma (1 - alpha_1) so that
                           the reference densities have equal pressure.  Needs
                           0 < alpha_1 < 1 and 0 < alpha_2 < 1 (LB_EINVAL)     */
+  double mass_tol;     /* mass-drift guard (>= 0; 0 = off): a recorded sample
+                          (obs_every) whose component mass differs from that
+                          of the first recorded sample after initialisation
+                          by more than mass_tol times the total mass raises
+                          flag bit 1 and makes lb_step / lb_observables return
+                          LB_ENUMERIC.  Both components are conserved exactly
+                          by the method (Eq. CGLBE streams and the collision
+                          keeps each rho^k), so drift means lost precision.  */
 } lb_params;
 
 /* Observables of the current state, accumulated in FP64 in a fixed order:
@@ -120,7 +128,9 @@ typedef struct {
  *   Q_d      = sum_x (rho1/rho) u_x / nx   (dispersed-phase flow rate)
  *   umax     = max_x |u|,  u = (j + F/2)/rho
  *   converged: windowed-Q test satisfied (conv_window > 0)
- *   flags    : bit 0 NaN/Inf seen                                          */
+ *   flags    : bit 0 NaN/Inf seen in any evaluated observable; bit 1 mass
+ *              drift beyond mass_tol at a recorded sample (sticky until the
+ *              next lb_init_fields / lb_set_populations)                 */
 typedef struct {
   int64_t step;
   double mass[2];
@@ -149,16 +159,35 @@ int lb_init_fields(lb_handle *h, const double *rho1, const double *rho2, const d
  * with the direction order of lb_lattice_tables.  Errors as lb_init_fields. */
 int lb_set_populations(lb_handle *h, const double *f1, const double *f2);
 
-/* Advance n >= 0 steps (collide, then pull-stream).  Asynchronous.
- * Errors: LB_ESTATE before initialisation, LB_EDEVICE on launch failure. */
+/* Advance n >= 0 steps of Eq. CGLBE (collide, then pull-stream; one step is
+ * the whole update of Materials and Methods: densities and psi, colour
+ * gradient, NCI force of Eq. near_c, BGK + perturbation + recolouring with
+ * exact-difference forcing, streaming).  Asynchronous on the handle's stream.
+ * Errors: LB_EINVAL (n < 0), LB_ESTATE before initialisation, LB_EDEVICE on
+ * launch failure, LB_ENUMERIC when a step recorded before this call (obs_every
+ * > 0) saw a NaN/Inf or a mass drift beyond mass_tol: the flags of recorded
+ * steps reach the host asynchronously, so a failure shows at the next
+ * lb_step after the stream has passed the recording, and always at
+ * lb_observables.  The steps of the failing call are not run. */
 int lb_step(lb_handle *h, int64_t n);
+/* Captures and instantiates, ahead of the first lb_step, the replay graphs
+ * lb_step uses for windows of plain steps (both ping-pong copies); optional,
+ * lb_step otherwise builds them on first use.  Runs no step and changes no
+ * state.  Returns LB_OK, or LB_EDEVICE if capture failed (lb_step then uses
+ * plain launches; its results are identical either way). */
+int lb_prepare(lb_handle *h);
+/* Measurement support: lb_step(h, n) bracketed by two HIP events recorded on
+ * the handle's stream; *ms receives the device time between them.
+ * Synchronises the stream.  Errors as lb_step; LB_EINVAL for a NULL ms. */
+int lb_step_timed(lb_handle *h, int64_t n, double *ms);
 /* 1 while lb_step replays windows of 16 plain steps (no observable recording
  * inside, profiling off) from a captured hipGraph, 0 after a capture failed
  * (plain launches from then on; the results are identical either way). */
 int lb_graphs(const lb_handle *h);
 
 /* Observables of the current state (synchronises the stream).
- * Returns LB_ENUMERIC if a NaN/Inf was seen (out is still filled). */
+ * Returns LB_ENUMERIC if a NaN/Inf or a mass drift was flagged (out is still
+ * filled). */
 int lb_observables(lb_handle *h, lb_obs *out);
 
 /* Current fields: rho1, rho2 (N doubles each) and the physical velocity
@@ -320,6 +349,10 @@ int lb_batch_init_fields(lb_batch *b, int32_t c, const double *rho1, const doubl
  * Errors: LB_ESTATE (uninitialised channel), LB_EDEVICE (launch failure or a
  * channel barrier that did not complete within its spin limit). */
 int lb_batch_step(lb_batch *b, int64_t n, int32_t mode);
+/* Flags of every channel (n int32, the lb_obs flags bits) after the last
+ * lb_batch_step, which returns LB_ENUMERIC when any channel has one set (the
+ * other channels have still taken their steps). */
+int lb_batch_flags(lb_batch *b, int32_t *flags);
 int lb_batch_observables(lb_batch *b, int32_t c, lb_obs *out);
 int lb_batch_get_fields(lb_batch *b, int32_t c, double *rho1, double *rho2, double *u);
 /* Steps completed by channel c, whether it is still active, and the number of

@@ -149,8 +149,13 @@ int dispatch(lb_handle *h, int mode, double *o0, double *o1, double *o2, int32_t
 
 int reduce_obs(lb_handle *h, int record) {
   hipLaunchKernelGGL(k_obs_reduce, dim3(1), dim3(256), 0, h->stream, h->partials, h->nparts,
-                     h->obs, 1.0 / h->p.nx, h->p.conv_window, h->p.conv_m, h->p.conv_eps, record);
+                     h->obs, 1.0 / h->p.nx, h->p.conv_window, h->p.conv_m, h->p.conv_eps,
+                     h->p.mass_tol, record);
   HIP_TRY(hipGetLastError());
+  // the flags of a recorded step travel to pinned host memory behind it, so
+  // lb_step can report them without synchronising
+  if (record && h->hflags)
+    HIP_TRY(hipMemcpyAsync(h->hflags, &h->obs->flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   return LB_OK;
 }
 
@@ -187,6 +192,7 @@ int validate(const lb_params *p) {
   }
   if (p->obs_every < 0 || p->conv_window < 0 || p->conv_m < 0 || !(p->conv_eps >= 0))
     return fail(LB_EINVAL, "bad observable/convergence settings");
+  if (!(p->mass_tol >= 0.0) || !std::isfinite(p->mass_tol)) return fail(LB_EINVAL, "mass_tol must be finite and >= 0");
   return LB_OK;
 }
 
@@ -219,6 +225,7 @@ int upload_explicit(lb_handle *h, const std::vector<double> &xt, const std::vect
   HIP_TRY(hipMemcpyAsync(h->xc, xc.data(), bytes, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemsetAsync(h->obs, 0, sizeof(ObsDev), h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  if (h->hflags) *h->hflags = 0;
   h->explicit_src = 1;
   h->initialised = 1;
   h->t = 0;
@@ -272,6 +279,11 @@ int lb_create(const lb_params *p, void *hip_stream, lb_handle **out) {
   if (!rc) rc = alloc(h, (void **)&h->partials, sizeof(double) * 8 * (size_t)h->nparts);
   if (!rc) rc = alloc(h, (void **)&h->obs, sizeof(ObsDev));
   if (!rc) {
+    hipError_t e = hipHostMalloc((void **)&h->hflags, sizeof(int32_t), hipHostMallocDefault);
+    if (e != hipSuccess) rc = fail(LB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    else *h->hflags = 0;
+  }
+  if (!rc) {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = fail(LB_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
   }
@@ -299,6 +311,7 @@ void lb_destroy(lb_handle *h) {
   (void)hipFree(h->xc);
   (void)hipFree(h->partials);
   (void)hipFree(h->obs);
+  if (h->hflags) (void)hipHostFree(h->hflags);
   analysis_free(h);
   geometry_free(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
@@ -378,29 +391,42 @@ int lb_set_populations(lb_handle *h, const double *f1, const double *f2) {
 // once per starting copy on a private stream, launched on the handle's stream.
 static constexpr int GRAPH_STEPS = 16;
 
-static int graph_steps(lb_handle *h) {
-  const int c0 = h->cur;
-  if (!h->graph[c0]) {
-    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    hipStream_t user = h->stream;
-    h->stream = h->cap_stream;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
-    int rc = LB_OK;
-    for (int k = 0; k < GRAPH_STEPS && e == hipSuccess && rc == LB_OK; ++k) rc = dispatch(h, STEP);
-    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
-    h->stream = user;
-    h->cur = c0;
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess && rc == LB_OK) e = hipGraphInstantiate(&h->graph[c0], g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    if (e != hipSuccess || rc != LB_OK) {
-      (void)hipGetLastError();
-      h->graph[c0] = nullptr;
-      return fail(LB_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-    }
+// Captures and instantiates the graph of GRAPH_STEPS plain (pulling) steps
+// starting from state copy c0, without running it.
+static int graph_capture(lb_handle *h, int c0) {
+  if (h->graph[c0]) return LB_OK;
+  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = h->stream;
+  const int cur = h->cur, xs = h->explicit_src;
+  const int prof = h->profile;
+  h->stream = h->cap_stream;
+  h->cur = c0;
+  h->explicit_src = 0;
+  h->profile = 0;  // no timing events inside a graph
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+  int rc = LB_OK;
+  for (int k = 0; k < GRAPH_STEPS && e == hipSuccess && rc == LB_OK; ++k) rc = dispatch(h, STEP);
+  hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+  h->stream = user;
+  h->cur = cur;
+  h->explicit_src = xs;
+  h->profile = prof;
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess && rc == LB_OK) e = hipGraphInstantiate(&h->graph[c0], g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess || rc != LB_OK) {
+    (void)hipGetLastError();
+    h->graph[c0] = nullptr;
+    return fail(LB_EDEVICE, "graph capture: %s", hipGetErrorString(e));
   }
-  HIP_TRY(hipGraphLaunch(h->graph[c0], h->stream));
+  return LB_OK;
+}
+
+static int graph_steps(lb_handle *h) {
+  int rc = graph_capture(h, h->cur);
+  if (rc) return rc;
+  HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream));
   return LB_OK;
 }
 
@@ -408,6 +434,8 @@ int lb_step(lb_handle *h, int64_t n) {
   if (!h) return fail(LB_EINVAL, "NULL handle");
   if (n < 0) return fail(LB_EINVAL, "negative step count");
   if (!h->initialised) return fail(LB_ESTATE, "lb_step before initialisation");
+  if (const int32_t fl = h->hflags ? *(volatile int32_t *)h->hflags : 0)
+    return fail(LB_ENUMERIC, "a recorded step flagged %s", (fl & 1) ? "a NaN/Inf" : "a mass drift beyond mass_tol");
   const int64_t oe = h->p.obs_every;
   for (int64_t k = 0; k < n;) {
     // a window of plain steps (no recording step inside) goes through a graph
@@ -430,6 +458,43 @@ int lb_step(lb_handle *h, int64_t n) {
     }
     h->t += 1;
     k += 1;
+  }
+  return LB_OK;
+}
+
+int lb_step_timed(lb_handle *h, int64_t n, double *ms) {
+  if (!h || !ms) return fail(LB_EINVAL, "NULL argument");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  int rc = e == hipSuccess ? LB_OK : fail(LB_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+  if (!rc) {
+    e = hipEventRecord(e0, h->stream);
+    if (e != hipSuccess) rc = fail(LB_EDEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+  }
+  if (!rc) rc = lb_step(h, n);
+  if (!rc) {
+    e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float f = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+    if (e != hipSuccess) rc = fail(LB_EDEVICE, "step timing: %s", hipGetErrorString(e));
+    *ms = f;
+  }
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int lb_prepare(lb_handle *h) {
+  if (!h) return fail(LB_EINVAL, "NULL handle");
+  if (!h->graphs_ok) return LB_OK;
+  for (int c = 0; c < 2; ++c) {
+    const int rc = graph_capture(h, c);
+    if (rc) {
+      h->graphs_ok = 0;
+      return rc;
+    }
   }
   return LB_OK;
 }
@@ -457,6 +522,7 @@ int lb_observables(lb_handle *h, lb_obs *out) {
   out->converged = o.converged;
   out->flags = o.flags;
   if (o.flags & 1) return fail(LB_ENUMERIC, "NaN/Inf in the observables");
+  if (o.flags & 2) return fail(LB_ENUMERIC, "component mass drifted beyond mass_tol");
   return LB_OK;
 }
 

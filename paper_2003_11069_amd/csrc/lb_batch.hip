@@ -42,6 +42,8 @@ struct lb_batch {
   int32_t *d_chan_of = nullptr, *d_rank_of = nullptr, *d_group = nullptr;
   uint32_t *d_bar = nullptr;
   int32_t *d_err = nullptr;
+  int32_t *d_flags = nullptr;    // [n] observable flags gathered after each lb_batch_step
+  std::vector<int32_t> flags;    // host copy
   int grid_persistent = 0;
   std::vector<int32_t> group;    // blocks per channel (persistent mode)
   std::vector<int32_t> xcd_of;   // XCD of each channel (persistent mode)
@@ -58,6 +60,13 @@ struct lb_batch {
 };
 
 namespace {
+
+// Copies the observable flags of every channel into one array.
+__global__ __launch_bounds__(256) void k_gather_flags(const ChanCtl *__restrict__ ctl, int n,
+                                                      int32_t *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) out[c] = ctl[c].obs->flags;
+}
 
 template <typename S, typename R>
 int build_tables_t(lb_batch *b) {
@@ -448,6 +457,7 @@ int lb_batch_create(const lb_params *p, int32_t n, void *hip_stream, lb_batch **
       k.W = h->p.conv_window;
       k.m = h->p.conv_m;
       k.eps = h->p.conv_eps;
+      k.mass_tol = h->p.mass_tol;
       k.obs_every = h->p.obs_every;
       k.parity = 0;
       b->ctl[c] = k;
@@ -460,6 +470,9 @@ int lb_batch_create(const lb_params *p, int32_t n, void *hip_stream, lb_batch **
     hipError_t e = hipMalloc(&b->d_bar, sizeof(uint32_t) * n);
     if (e == hipSuccess) e = hipMalloc(&b->d_err, sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&b->d_flags, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipMemset(b->d_flags, 0, sizeof(int32_t) * n);
+    b->flags.assign(n, 0);
     if (e != hipSuccess) rc = fail(LB_EDEVICE, "batch tables: %s", hipGetErrorString(e));
   }
   if (!rc) rc = build_groups(b);
@@ -486,6 +499,7 @@ void lb_batch_destroy(lb_batch *b) {
   (void)hipFree(b->d_group);
   (void)hipFree(b->d_bar);
   (void)hipFree(b->d_err);
+  (void)hipFree(b->d_flags);
   for (lb_handle *h : b->h) lb_destroy(h);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -549,6 +563,11 @@ int lb_batch_step(lb_batch *b, int64_t n, int32_t mode) {
                                          b->stream));
     }
   }
+  hipLaunchKernelGGL(k_gather_flags, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->d_ctl, b->n,
+                     b->d_flags);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(b->flags.data(), b->d_flags, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost,
+                         b->stream));
   rc = download_ctl(b);
   if (rc) return rc;
   if (mode == LB_BATCH_PERSISTENT && steps > 0) {
@@ -556,6 +575,21 @@ int lb_batch_step(lb_batch *b, int64_t n, int32_t mode) {
     HIP_TRY(hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost));
     if (err) return fail(LB_EDEVICE, "persistent launch: a channel barrier timed out");
   }
+  int bad = 0, first = -1;
+  for (int c = 0; c < b->n; ++c)
+    if (b->flags[c]) {
+      if (first < 0) first = c;
+      ++bad;
+    }
+  if (bad)
+    return fail(LB_ENUMERIC, "%d channel(s) flagged a NaN/Inf or mass drift (first: channel %d, flags %d)", bad,
+                first, b->flags[first]);
+  return LB_OK;
+}
+
+int lb_batch_flags(lb_batch *b, int32_t *flags) {
+  if (!b || !flags) return fail(LB_EINVAL, "NULL argument");
+  for (int c = 0; c < b->n; ++c) flags[c] = b->flags[c];
   return LB_OK;
 }
 
@@ -607,11 +641,15 @@ int lb_batch_tune(lb_batch *b, int32_t trial_steps, double *best_ms_per_step) {
   HIP_TRY(hipEventCreate(&e1));
   int rc = LB_OK;
   for (const Cand &c : cands) {
+    // a channel that goes non-finite does not stop the timing (the flag
+    // stays set and the next lb_batch_step reports it)
     rc = apply_config(b, c.mode, c.order, c.by);
     if (!rc) rc = lb_batch_step(b, 2, c.mode);  // warm-up (also records the graph)
+    if (rc == LB_ENUMERIC) rc = LB_OK;
     if (rc) break;
     HIP_TRY(hipEventRecord(e0, b->stream));
     rc = lb_batch_step(b, trial_steps, c.mode);
+    if (rc == LB_ENUMERIC) rc = LB_OK;
     if (rc) break;
     HIP_TRY(hipEventRecord(e1, b->stream));
     HIP_TRY(hipEventSynchronize(e1));

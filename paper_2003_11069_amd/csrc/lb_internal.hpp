@@ -80,6 +80,7 @@ struct lb_handle {
   double *partials = nullptr;
   int nparts = 0;
   lbk::ObsDev *obs = nullptr;
+  int32_t *hflags = nullptr;  // pinned host copy of obs->flags after each recorded step
   int cur = 0;
   int initialised = 0;
   int explicit_src = 0;

@@ -841,7 +841,9 @@ __global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) 
 // strided order, then a fixed tree), followed by the windowed flow-rate
 // convergence test: the mean Q over a window of W samples is compared with the
 // previous window's; converged after m consecutive windows with a relative
-// change <= eps.
+// change <= eps.  A recorded sample whose component masses moved from those of
+// the first recorded sample by more than mass_tol times the total mass
+// (mass_tol > 0) raises the mass-drift flag.
 struct ObsDev {
   double v[8];        // M1, M2, Px, Py, Pz, Q (unnormalised), Qd, umax
   double win_sum;     // running sum of Q in the current window
@@ -851,15 +853,16 @@ struct ObsDev {
   int32_t n_windows;  // complete windows so far
   int32_t consec;     // consecutive windows within eps
   int32_t converged;
-  int32_t flags;
-  int32_t pad;
+  int32_t flags;      // bit 0: NaN/Inf seen; bit 1: component mass drifted
+  int32_t n_rec;      // recorded samples since initialisation
+  double m_ref[2];    // component masses of the first recorded sample
 };
 
 // One 256-thread block reduces nparts per-tile partials (fixed order) into o
 // and, when record != 0, advances the windowed flow-rate test.
 __device__ __forceinline__ void obs_reduce_block(const double *partials, int nparts, ObsDev *o,
                                                  double inv_nx, int W, int m, double eps,
-                                                 int record, double (*sh)[8]) {
+                                                 double mass_tol, int record, double (*sh)[8]) {
   const int t = threadIdx.x + blockDim.x * threadIdx.y;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int p = t; p < nparts; p += 256)
@@ -881,6 +884,16 @@ __device__ __forceinline__ void obs_reduce_block(const double *partials, int npa
     bool bad = false;
     for (int k = 0; k < 8; ++k) bad |= !isfinite(o->v[k]);
     if (bad) o->flags |= 1;
+    if (record) {
+      if (o->n_rec == 0) {
+        o->m_ref[0] = o->v[0];
+        o->m_ref[1] = o->v[1];
+      } else if (mass_tol > 0) {
+        const double tol = mass_tol * (fabs(o->m_ref[0]) + fabs(o->m_ref[1]));
+        if (!(fabs(o->v[0] - o->m_ref[0]) <= tol && fabs(o->v[1] - o->m_ref[1]) <= tol)) o->flags |= 2;
+      }
+      o->n_rec += 1;
+    }
     if (record && W > 0) {
       o->win_sum += o->v[5];
       o->win_count += 1;
@@ -903,9 +916,9 @@ __device__ __forceinline__ void obs_reduce_block(const double *partials, int npa
 
 static __global__ __launch_bounds__(256) void k_obs_reduce(const double *partials, int nparts,
                                                     ObsDev *o, double inv_nx, int W, int m,
-                                                    double eps, int record) {
+                                                    double eps, double mass_tol, int record) {
   __shared__ double sh[256][8];
-  obs_reduce_block(partials, nparts, o, inv_nx, W, m, eps, record, sh);
+  obs_reduce_block(partials, nparts, o, inv_nx, W, m, eps, mass_tol, record, sh);
 }
 
 // Streaming copy used as the achievable-bandwidth reference: one 16-byte
@@ -947,6 +960,7 @@ struct ChanCtl {
   double inv_nx;
   int32_t W, m;
   double eps;
+  double mass_tol;
   int32_t obs_every;
   int32_t parity;       // state copy holding the current state
 };
@@ -994,7 +1008,7 @@ static __global__ __launch_bounds__(256) void k_batch_end(ChanCtl *ctl) {
   ChanCtl &c = ctl[blockIdx.x];
   if (!c.active) return;
   const bool rec = c.obs_every > 0 && (c.t % c.obs_every) == 0;
-  if (rec) obs_reduce_block(c.partials, c.n_main, c.obs, c.inv_nx, c.W, c.m, c.eps, 1, sh);
+  if (rec) obs_reduce_block(c.partials, c.n_main, c.obs, c.inv_nx, c.W, c.m, c.eps, c.mass_tol, 1, sh);
   __syncthreads();
   if (threadIdx.x == 0) {
     c.t += 1;
@@ -1019,7 +1033,8 @@ __device__ __forceinline__ bool group_barrier(uint32_t *cnt, uint32_t target, in
     int ok = 1;
     uint32_t spins = 0;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz constant clock
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    // wrap-safe: arrivals grow by 2 g per step and may pass 2^32 in a long launch
+    while ((int32_t)(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1u << 26) || __builtin_amdgcn_s_memrealtime() - t0 > 200000000ull ||
           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -1088,7 +1103,7 @@ __global__ __launch_bounds__(256) void k_persistent(const Args<S, R> *__restrict
     arrivals += g;
     if (!group_barrier(cnt, arrivals, err, &flag)) break;
     if (rank == 0) {
-      if (rec) obs_reduce_block(c.partials, c.n_main, c.obs, c.inv_nx, c.W, c.m, c.eps, 1, sh);
+      if (rec) obs_reduce_block(c.partials, c.n_main, c.obs, c.inv_nx, c.W, c.m, c.eps, c.mass_tol, 1, sh);
       if (threadIdx.x == 0 && threadIdx.y == 0) {
         c.t += 1;
         c.parity = par ^ 1;

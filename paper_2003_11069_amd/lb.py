@@ -37,7 +37,8 @@ class lb_params(C.Structure):
                 ("h_max", C.c_double), ("force", C.c_double * 3), ("storage", C.c_int32),
                 ("obs_every", C.c_int32), ("conv_window", C.c_int32), ("conv_m", C.c_int32),
                 ("conv_eps", C.c_double), ("tau2", C.c_double),
-                ("nci_mode", C.c_int32), ("rho_ratio", C.c_double), ("alpha1", C.c_double)]
+                ("nci_mode", C.c_int32), ("rho_ratio", C.c_double), ("alpha1", C.c_double),
+                ("mass_tol", C.c_double)]
 
 
 class lb_obs(C.Structure):
@@ -68,6 +69,8 @@ def load_library(path: str = LIB_PATH):
         "lb_init_fields": ([vp, dp, dp, dp], C.c_int),
         "lb_set_populations": ([vp, dp, dp], C.c_int),
         "lb_step": ([vp, C.c_int64], C.c_int),
+        "lb_prepare": ([vp], C.c_int),
+        "lb_step_timed": ([vp, C.c_int64, dp], C.c_int),
         "lb_graphs": ([vp], C.c_int),
         "lb_observables": ([vp, P(lb_obs)], C.c_int),
         "lb_get_fields": ([vp, dp, dp, dp], C.c_int),
@@ -91,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "lb_batch_create": ([P(lb_params), C.c_int32, vp, P(vp)], C.c_int),
         "lb_batch_init_fields": ([vp, C.c_int32, dp, dp, dp], C.c_int),
         "lb_batch_step": ([vp, C.c_int64, C.c_int32], C.c_int),
+        "lb_batch_flags": ([vp, ip], C.c_int),
         "lb_batch_observables": ([vp, C.c_int32, P(lb_obs)], C.c_int),
         "lb_batch_get_fields": ([vp, C.c_int32, dp, dp, dp], C.c_int),
         "lb_batch_info": ([vp, C.c_int32, P(C.c_int64), P(C.c_int32), P(C.c_int32)], C.c_int),
@@ -198,6 +202,7 @@ class Params:
     nci_mode: int = 0
     rho_ratio: float = 0.0
     alpha1: float = 0.0
+    mass_tol: float = 0.0
 
     @classmethod
     def from_dict(cls, d: dict, **kw):
@@ -292,6 +297,18 @@ class Lattice:
 
     def step(self, n: int = 1):
         _check(self.lib.lb_step(self.h, int(n)))
+
+    def step_timed(self, n: int) -> float:
+        """lb_step_timed: n steps between HIP events on the handle's stream;
+        returns their device time in ms (synchronises)."""
+        ms = C.c_double()
+        _check(self.lib.lb_step_timed(self.h, int(n), C.byref(ms)))
+        return ms.value
+
+    def prepare(self):
+        """lb_prepare: capture the step-replay graphs now instead of inside
+        the first lb_step that uses them."""
+        _check(self.lib.lb_prepare(self.h))
 
     def observables(self) -> dict:
         o = lb_obs()
@@ -398,8 +415,21 @@ class Batch:
         uu = None if u is None else np.ascontiguousarray(u, np.float64).ravel()
         _check(self.lib.lb_batch_init_fields(self.h, int(c), _dp(r1), _dp(r2), _dp(uu)))
 
-    def step(self, n: int, mode: int = 2):
-        _check(self.lib.lb_batch_step(self.h, int(n), int(mode)))
+    def step(self, n: int, mode: int = 2, numeric_ok: bool = False) -> list:
+        """Advances every active channel by n steps.  A channel flagged with a
+        NaN/Inf or a mass drift (LB_ENUMERIC) raises, unless numeric_ok: then
+        the flagged channels' indices are returned (the others stepped)."""
+        rc = self.lib.lb_batch_step(self.h, int(n), int(mode))
+        if rc == -4 and numeric_ok:
+            return [c for c, f in enumerate(self.flags()) if f]
+        _check(rc)
+        return []
+
+    def flags(self) -> np.ndarray:
+        """lb_batch_flags: the lb_obs flag bits of every channel."""
+        out = np.zeros(len(self.params), np.int32)
+        _check(self.lib.lb_batch_flags(self.h, _ip(out)))
+        return out
 
     def observables(self, c: int) -> dict:
         o = lb_obs()

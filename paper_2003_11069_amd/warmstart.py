@@ -158,7 +158,7 @@ def run_channels(specs_cases, inits=None, cap=100_000, chunk=WINDOW, keep_fields
     active = np.ones(n, bool)
     t, t0 = 0, time.perf_counter()
     while t < cap and active.any():
-        b.step(chunk, mode)
+        b.step(chunk, mode, numeric_ok=True)  # non-finite runs are dropped below
         t += chunk
         for k in np.flatnonzero(active):
             inf = b.info(k)

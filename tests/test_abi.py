@@ -56,7 +56,8 @@ BAD = [dict(tau=0.5), dict(tau=0.3), dict(beta=1.5), dict(beta=-0.1), dict(nx=0)
        dict(storage=7), dict(lattice=5), dict(walls_y=1, ny=2), dict(A_s=-0.1), dict(tau2=0.4),
        dict(tau2=-1.0), dict(nci_mode=2), dict(nci_mode=-1),
        dict(rho_ratio=2.0, alpha1=0.3), dict(rho_ratio=-1.0), dict(rho_ratio=2.0, alpha1=1.0),
-       dict(rho_ratio=3.0, alpha1=0.5)]
+       dict(rho_ratio=3.0, alpha1=0.5), dict(mass_tol=-1.0), dict(mass_tol=float("nan")),
+       dict(mass_tol=float("inf"))]
 
 
 @pytest.mark.parametrize("bad", BAD)
