@@ -284,7 +284,9 @@ static void node_nci(const lbo_params *p, int Q, int32_t (*c)[3], const double *
   double g = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
   Frep[0] = Frep[1] = Frep[2] = 0;
   *hit = 0;
-  double mg = INFINITY;
+  /* |G| enters the margin: whether the probe runs at all (G != 0) and the
+   * direction n = -G/|G| it follows are ill-conditioned as |G| -> 0 */
+  double mg = p->A_nci > 0 ? g : INFINITY;
   if (p->A_nci > 0 && g > 0 && p->nci_mode == 1) {
     /* continuous-NCI variant: first s with psi(x + s n) >= psi(x), h at the
      * linear crossing between samples s-1 and s (h = 1 for s = 1) */

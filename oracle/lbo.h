@@ -100,8 +100,10 @@ void lbo_observables(lbo *h, double out[8]);
 
 /* per-node diagnostics at the current time: psi (N, walls carry the copied
  * value), G (3N), F_rep (3N), hit distance h (N, 0 = none), and the decision
- * margin (N): the smallest |psi(y_s) - psi(x)| over probed sites and the
- * smallest distance of a probed s*n component to a rounding tie. */
+ * margin (N): the smallest of |G| (the probe's existence and direction are
+ * ill-conditioned as |G| -> 0), |psi(y_s) - psi(x)| over probed sites and the
+ * distance of a probed s*n component to a rounding tie; infinity when NCI is
+ * off. */
 void lbo_diagnostics(lbo *h, double *psi, double *G, double *Frep, int32_t *hit,
                      double *margin);
 

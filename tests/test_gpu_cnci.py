@@ -83,4 +83,5 @@ def test_fp16_storage_within_budget():
     g.step(200)
     e = field_errors(o, g, fluid_mask(case.params, case.N))
     say(f"  errors {e}")
-    assert e["rho1"] <= 2e-3 and e["rho2"] <= 2e-3 and e["u"] <= 0.2
+    # budget: about three times the measured rho 1.5e-5, u 3.1e-4
+    assert e["rho1"] <= 4.5e-5 and e["rho2"] <= 4.5e-5 and e["u"] <= 9.3e-4

@@ -45,7 +45,8 @@ def test_free_run_parity_200(name):
 def test_fp16_within_budget():
     """The deviations s = f/w - 1 of the lighter phase are about 1/gamma - 1
     rather than near 0, so FP16 storage rounds them more coarsely than at
-    equal densities: the budget here is 1e-2 on the densities."""
+    equal densities: the budget here is about three times the measured
+    rho 3.4e-3, u 6.1e-2."""
     make, gamma, a1 = CASES["two_droplets_g2"]
     case = _ratio_case(make(), gamma)
     say("[gpu] density ratio 2, FP16 storage, 200 steps")
@@ -54,7 +55,7 @@ def test_fp16_within_budget():
     g.step(200)
     e = field_errors(o, g, fluid_mask(case.params, case.N))
     say(f"  errors {e}")
-    assert e["rho1"] <= 1e-2 and e["rho2"] <= 1e-2 and e["u"] <= 0.2
+    assert e["rho1"] <= 1e-2 and e["rho2"] <= 1e-2 and e["u"] <= 0.18
 
 
 @pytest.mark.parametrize("gamma,a1", [(2.0, 0.8), (4.0, 0.9)])

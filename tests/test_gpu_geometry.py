@@ -73,7 +73,8 @@ def test_flow_focuser_fp16_within_budget():
     g.step(400)
     e = field_errors(o, g, case.info["type"] == synth.FLUID)
     say(f"  errors {e}")
-    assert e["rho1"] <= 2e-3 and e["rho2"] <= 2e-3 and e["u"] <= 0.2
+    # budget: about three times the measured rho 7.1e-5, u 5.7e-4
+    assert e["rho1"] <= 2.1e-4 and e["rho2"] <= 2.1e-4 and e["u"] <= 1.7e-3
 
 
 def test_mask_walls_equal_builtin_walls():

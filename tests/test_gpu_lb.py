@@ -55,12 +55,21 @@ def test_free_run_parity_200(name):
     g.step(200)
     mask = fluid_mask(case.params, case.N)
     e = field_errors(o, g, mask)
-    # flip census: NCI hit decisions that differ between the two sides
+    # flip census: NCI hit decisions that differ between the two sides.  A
+    # decision may differ only where the oracle's decision margin (the
+    # smallest of |G|, |psi(y_s) - psi(x)| over the probed sites and the
+    # distance of s n to a rounding tie; Eq. near_c's h is discontinuous
+    # there) is below 1e-5, or where both hit distances give the same A_h
     psi_g, fr_g, hit_g = g.nci()
-    hit_o = o.diagnostics()["hit"]
-    flips = int((hit_g != hit_o)[mask].sum())
-    say(f"  errors {e}  nci-flips {flips}")
+    dg = o.diagnostics()
+    hit_o, margin = dg["hit"], dg["margin"]
+    p = case.params
+    ah = lambda h: oracle.A_h(float(h), p["A_nci"], p["h_min"], p["h_max"]) if h else 0.0
+    diff = np.flatnonzero((hit_g != hit_o) & mask)
+    bad = [n for n in diff if not (margin[n] < 1e-5 or ah(hit_g[n]) == ah(hit_o[n]))]
+    say(f"  errors {e}  nci-flips {len(diff)} (margin >= 1e-5 with a different A_h: {len(bad)})")
     assert e["rho1"] <= TOL and e["rho2"] <= TOL and e["u"] <= TOL
+    assert not bad, [(int(n), int(hit_g[n]), int(hit_o[n]), float(margin[n])) for n in bad[:10]]
 
 
 @pytest.mark.parametrize("name", ["two_droplets_nci", "channel_3d_70x21x9"])
@@ -176,7 +185,8 @@ def test_two_tau_parity(storage):
     channel against the oracle after 200 steps (FP32 at the 1e-5 bar; FP16
     within its stated budget), and the tau2 = tau run equal to tau2 = 0."""
     say(f"[gpu] two relaxation times, {storage}")
-    tol_r, tol_u = (1e-5, 1e-5) if storage == "fp32" else (2e-3, 0.2)
+    # FP16: about three times the measured rho 1.7e-5, u 1.7e-3
+    tol_r, tol_u = (1e-5, 1e-5) if storage == "fp32" else (5.1e-5, 5e-3)
     for case in (synth.two_layer_channel(tau1=1.0, tau2=2.0, force=1e-5),
                  synth.channel_2d(synth.channel_spec(104, Lx=64, Ly=50), jitter=0.5)):
         params = dict(case.params)
@@ -234,11 +244,14 @@ def test_free_run_config2_20_steps():
     assert e["rho1"] <= TOL and e["rho2"] <= TOL and e["u"] <= TOL
 
 
-@pytest.mark.parametrize("storage,tol_rho,tol_u", [("fp32_f32", 1e-4, 1e-2), ("fp16", 2e-3, 0.2),
-                                                    ("bf16", 2e-2, 1.0)])
+# error budgets: about three times the errors measured on this case (FP32
+# arithmetic: rho 9.6e-6, u 5.2e-6; FP16: 1.4e-5, 2.4e-4; BF16: 1.1e-4,
+# 2.3e-3; component mass drift 1.5e-6 for all three)
+@pytest.mark.parametrize("storage,tol_rho,tol_u", [("fp32_f32", 3e-5, 1.6e-5), ("fp16", 4.2e-5, 7.2e-4),
+                                                    ("bf16", 3.3e-4, 7e-3)])
 def test_reduced_precision_error_bounds(storage, tol_rho, tol_u):
     """FP16/BF16 deviation storage and FP32 arithmetic: error against the FP64
-    oracle after 200 steps (reported; bounds are the stated error budget)."""
+    oracle after 200 steps, within the stated error budget."""
     case = CASES["channel_2d_160x50"]
     say(f"[gpu] storage {storage}")
     o, g = make_pair(case, storage=storage)
@@ -249,7 +262,7 @@ def test_reduced_precision_error_bounds(storage, tol_rho, tol_u):
     m1 = g.observables()["mass"]
     say(f"  errors {e} mass drift {(m1 - m0) / m0}")
     assert e["rho1"] <= tol_rho and e["rho2"] <= tol_rho and e["u"] <= tol_u
-    np.testing.assert_allclose(m1, m0, rtol=1e-5)
+    np.testing.assert_allclose(m1, m0, rtol=4.5e-6)
 
 
 def test_convergence_flag_poiseuille():

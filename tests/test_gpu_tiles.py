@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 
 STEPS = 100
 # storage -> (rho bound, u bound): FP32 the parity bar, FP16 the stated budget
-BOUNDS = {"fp32": (1e-5, 1e-5), "fp16": (2e-3, 0.2)}
+# (about three times the measured rho 1.7e-5, u 6.1e-4)
+BOUNDS = {"fp32": (1e-5, 1e-5), "fp16": (5e-5, 1.8e-3)}
 
 CASES = [
     # (lattice, nx, ny, nz, walls, storage)
