@@ -145,7 +145,11 @@ typedef struct {
  * (NULL = default stream) on which all work of the handle is enqueued.
  * Errors: LB_EINVAL (tau <= 1/2, beta outside [0,1], sizes <= 0, nz != 1 with
  * D2Q9, walls with ny < 3, h_min > h_max, h_max > 4 or h_min <= 0, A_nci < 0,
- * unknown storage), LB_ENOMEM, LB_EDEVICE. */
+ * unknown storage, more than 2^29 nodes), LB_ENOMEM, LB_EDEVICE.  Device
+ * memory per node (two state copies plus psi and rho1): D3Q27 about 272 B
+ * with FP32 storage and 152 B with FP16/BF16, so 2^29 nodes fit in 288 GB
+ * (lb_init_fields / lb_set_populations hold 2 Q FP64 values per node more
+ * until the first lb_step has consumed them). */
 int lb_create(const lb_params *p, void *hip_stream, lb_handle **out);
 
 /* Initial state f_i^k(x,0) = E_i(rho^k(x), u(x)) with the second-order

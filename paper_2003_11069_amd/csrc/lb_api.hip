@@ -184,12 +184,6 @@ int validate(const lb_params *p) {
     if (!std::isfinite(p->force[d])) return fail(LB_EINVAL, "force must be finite");
   if (p->storage < LB_STORE_FP32 || p->storage > LB_STORE_FP32_F32)
     return fail(LB_EINVAL, "unknown storage %d", p->storage);
-  {  // the stored deviations of all directions are addressed with 32-bit byte offsets
-    const uint64_t Q = p->lattice == LB_D2Q9 ? 9 : 27;
-    const uint64_t sb = (p->storage == LB_STORE_FP16_DEV || p->storage == LB_STORE_BF16_DEV) ? 2 : 4;
-    if (Q * sb * (uint64_t)p->nx * p->ny * p->nz >= ((uint64_t)1 << 32))
-      return fail(LB_EINVAL, "lattice too large: Q*N*element size must stay below 4 GiB");
-  }
   if (p->obs_every < 0 || p->conv_window < 0 || p->conv_m < 0 || !(p->conv_eps >= 0))
     return fail(LB_EINVAL, "bad observable/convergence settings");
   if (!(p->mass_tol >= 0.0) || !std::isfinite(p->mass_tol)) return fail(LB_EINVAL, "mass_tol must be finite and >= 0");
@@ -450,8 +444,20 @@ int lb_step(lb_handle *h, int64_t n) {
       h->graphs_ok = 0;  // fall back to plain launches from now on
     }
     const bool rec = oe > 0 && (h->t % oe) == 0;
+    const bool first = h->explicit_src != 0;
     int rc = dispatch(h, rec ? STEP_OBS : STEP);
     if (rc) return rc;
+    if (first) {
+      // the explicit initial state (2 Q FP64 values per node) has been
+      // consumed: release it once that step is done (the next lb_init_fields
+      // or lb_set_populations allocates it again)
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      const int64_t bytes = (int64_t)(2 * sizeof(double) * (size_t)h->Q * (size_t)h->N);
+      HIP_TRY(hipFree(h->xt));
+      HIP_TRY(hipFree(h->xc));
+      h->xt = h->xc = nullptr;
+      h->bytes -= bytes;
+    }
     if (rec) {
       rc = reduce_obs(h, 1);
       if (rc) return rc;

@@ -30,7 +30,8 @@
 //             total populations, BGK + EDM + perturbation + recolouring ->
 //             store (or FP64 observables, fields or populations instead)
 // Indexing is 32-bit (the library limits N to 2^29 nodes) so that loads use a
-// uniform base register plus a 32-bit per-lane offset.
+// uniform base register plus a 32-bit per-lane offset; the stored deviations
+// take one 64-bit base per direction.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
@@ -225,6 +226,14 @@ __device__ __forceinline__ void stb_out(T *base, uint32_t byte_off, T v) {
   }
 }
 
+// Base of direction i's block of N stored deviations: a 64-bit pointer per
+// direction, so every byte offset inside a direction stays 32-bit and the
+// lattice needs only N * sizeof(S) < 4 GiB (not Q N sizeof(S)).
+template <typename T>
+__device__ __forceinline__ T *dir_base(T *s, uint32_t N, int i) {
+  return s + (size_t)i * N;
+}
+
 template <typename T>
 __device__ __forceinline__ T ldb(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (size_t)byte_off);
@@ -264,7 +273,7 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
   j[0] = j[1] = j[2] = 0;
   const Wrap wr = make_wrap(A.nx, A.ny, A.nz, A.walls, x, y, z);
   const Offs of = make_offs<D, SB>(A.nx, A.ny, A.nz, A.walls, x, y, z);
-  const uint32_t nb = n * SB, NB = A.N * SB;
+  const uint32_t nb = n * SB;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
@@ -276,7 +285,7 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
       if (COL != COL_NONE) c1 = (R)A.xc[(size_t)i * A.N + n];
     } else {
       if (!is_fp32<S>::value && i == L::REST) sv = ld(A.in.s0, n);
-      else sv = to_f(ldb(A.in.s, nb + of.x[cx + 1] + of.y[cy + 1] + of.z[cz + 1] + (uint32_t)i * NB));
+      else sv = to_f(ldb(dir_base(A.in.s, A.N, i), nb + of.x[cx + 1] + of.y[cy + 1] + of.z[cz + 1]));
       if (COL != COL_NONE) {
         const bool bb = GEOM ? ((gm >> i) & 1u) != 0u
                              : (A.walls && cy != 0 && (y - cy == 0 || y - cy == A.ny - 1));
@@ -745,7 +754,7 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       // phase are O(1 - 1/gamma), so this rounding matches their storage's)
       const float dnrf = (float)(r1 * A.dr_g1 + (rho - r1) * A.dr_g2);
       const float cdr = om * (drf + dnrf) - pg * (1.0f / 3.0f);
-      const uint32_t nb = n * (uint32_t)sizeof(S), NB = A.N * (uint32_t)sizeof(S);
+      const uint32_t nb = n * (uint32_t)sizeof(S);
       Offs go{};  // geometry: wrapped byte offsets of the neighbours (periodic)
       if constexpr (GEOM) go = make_offs<D, (uint32_t)sizeof(S)>(A.nx, A.ny, A.nz, 0, x, y, z);
       R sum_q = 0;
@@ -763,13 +772,13 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         const float sn_i = omc * f[i] + C + O;
         const float sn_o = omc * f[io] + C - O;
         const S q_i = from_f<S>(sn_i), q_o = from_f<S>(sn_o);
-        stb_out<1>(A.out.s, nb + (uint32_t)i * NB, q_i);
-        stb_out<1>(A.out.s, nb + (uint32_t)io * NB, q_o);
+        stb_out<1>(dir_base(A.out.s, A.N, i), nb, q_i);
+        stb_out<1>(dir_base(A.out.s, A.N, io), nb, q_o);
         // populations heading into a wall: reflected copy into the wall row,
         // node x + c_d, slot opp(d) (direction i has c_y = icy, opp(i) -icy)
         auto ghost = [&](int d, int dcx, int dcy, int dcz, S q) {
           const Offs wo = make_offs<D, (uint32_t)sizeof(S)>(A.nx, A.ny, A.nz, 1, x, y, z);
-          stb_out<1>(A.out.s, nb + wo.x[1 - dcx] + wo.y[1 - dcy] + wo.z[1 - dcz] + (uint32_t)L::opp(d) * NB, q);
+          stb_out<1>(dir_base(A.out.s, A.N, L::opp(d)), nb + wo.x[1 - dcx] + wo.y[1 - dcy] + wo.z[1 - dcz], q);
         };
         if constexpr (GEOM) {
           // populations heading into a solid node x + c_d: reflected copy in
@@ -777,7 +786,7 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
           // is the pull source of -c_d, so its byte offset is go.*[1 - c_d]
           auto ghost_g = [&](int d, int dcx, int dcy, int dcz, S q) {
             const uint32_t nwb = nb + go.x[1 - dcx] + go.y[1 - dcy] + go.z[1 - dcz];
-            stb_out<1>(A.out.s, nwb + (uint32_t)L::opp(d) * NB, q);
+            stb_out<1>(dir_base(A.out.s, A.N, L::opp(d)), nwb, q);
           };
           if ((gm >> io) & 1u) ghost_g(i, icx, icy, icz, q_i);
           if ((gm >> i) & 1u) ghost_g(io, -icx, -icy, -icz, q_o);
@@ -788,7 +797,7 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         sum_q += (R)L::w(i) * ((R)to_f(q_i) + (R)to_f(q_o));
       }
       const float srest = (float)((dr - sum_q) * (R)(1.0 / L::w(L::REST)));
-      if (is_fp32<S>::value) stb_out<1>(A.out.s, nb + (uint32_t)L::REST * NB, from_f<S>(srest));
+      if (is_fp32<S>::value) stb_out<1>(dir_base(A.out.s, A.N, L::REST), nb, from_f<S>(srest));
       else stb_out<1>(A.out.s0, n * 4u, srest);
       const R dr_t = sum_q + (R)L::w(L::REST) * (R)srest;
       stb_out<2>(A.out.a, n * (uint32_t)sizeof(R), r1 / ((R)1 + dr_t));
