@@ -34,6 +34,8 @@ import math
 import os
 import sys
 import time
+import dataclasses
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -43,14 +45,39 @@ if __package__ in (None, ""):
 import synth  # noqa: E402
 from paper_2003_11069_amd import lb, ws  # noqa: E402
 
-H, W = 128, 256  # image rows (y, walls at 0 and H-1) and columns (x, periodic)
-WINDOW = 500     # steps per flow-rate window: 50 samples, one every 10 steps
-CONV = dict(obs_every=10, conv_window=WINDOW // 10, conv_m=3, conv_eps=1e-4)
+@dataclass(frozen=True)
+class Setup:
+    """Channel size, parameter ranges and convergence settings of a
+    warm-start workload.  The channels come from the batched-sweep generator
+    (synth.channel_spec) at a fixed size, its draws mapped onto the given
+    ranges of pressure gradient, NCI strength and droplet radius."""
+    H: int = 128          # image rows (y, walls at 0 and H-1)
+    W: int = 256          # image columns (x, periodic)
+    G_range: tuple = (1e-6, 1e-4)
+    A_range: tuple = (0.0, 0.05)
+    R_range: tuple = (10, 20)
+    window: int = 500     # steps per flow-rate window
+    obs_every: int = 10   # steps between flow-rate samples
+    conv_m: int = 3
+    conv_eps: float = 1e-4
+
+    @property
+    def conv(self) -> dict:
+        return dict(obs_every=self.obs_every, conv_window=self.window // self.obs_every,
+                    conv_m=self.conv_m, conv_eps=self.conv_eps)
+
+
+FULL = Setup()                                         # the 256 x 128 workload
+SMALL = Setup(H=64, W=128, R_range=(5, 10), window=250)  # the same geometry at half scale
+H, W = FULL.H, FULL.W
+WINDOW = FULL.window
+CONV = FULL.conv
 U_CLIP = 1.5     # bound on predicted |u_x|, |u_y| in units of u_ref
 
 
-def make_case(seed: int):
-    spec = synth.channel_spec(seed, Lx=W, Ly=H)
+def make_case(seed: int, st: Setup = FULL):
+    spec = synth.channel_spec(seed, Lx=st.W, Ly=st.H, G_range=st.G_range, A_range=st.A_range,
+                              R_range=st.R_range)
     return spec, synth.channel_2d(spec)
 
 
@@ -63,6 +90,7 @@ def u_ref(spec) -> float:
 
 def net_input(spec, case) -> np.ndarray:
     """[H, W, 3] float32: psi0, (log10 G_p + 5), A_nci / 0.025 - 1."""
+    H, W = spec.Ly, spec.Lx
     r1 = case.rho1.reshape(H, W)
     r2 = case.rho2.reshape(H, W)
     psi = np.where(r1 + r2 > 0, (r1 - r2) / np.maximum(r1 + r2, 1e-300), -1.0)
@@ -76,6 +104,7 @@ def net_input(spec, case) -> np.ndarray:
 
 def net_target(spec, rho1, rho2, u) -> np.ndarray:
     """[H, W, 3] float32: steady psi, u_x / u_ref, u_y / u_ref (walls: -1, 0, 0)."""
+    H, W = spec.Ly, spec.Lx
     r1 = rho1.reshape(H, W)
     r2 = rho2.reshape(H, W)
     rho = r1 + r2
@@ -101,6 +130,7 @@ def init_from_prediction(spec, case, pred: np.ndarray, phase=True, velocity=True
     steady speed never exceeds the Poiseuille centre-line speed by much; the
     clip keeps a poor prediction from starting an unstable run).  Unused
     parts come from the plain start."""
+    H, W = spec.Ly, spec.Lx
     N = H * W
     pred = np.nan_to_num(pred, nan=0.0, posinf=0.0, neginf=0.0)
     fluid = np.zeros((H, W), bool)
@@ -131,21 +161,25 @@ def init_from_prediction(spec, case, pred: np.ndarray, phase=True, velocity=True
     return r1, r2, u
 
 
-def perturbed_start(spec, case, amp=1e-3):
+def perturbed_start(spec, case, amp=1e-3, noise_seed=0):
     """Plain start plus white-noise velocity of amplitude amp * u_ref."""
-    rng = np.random.Generator(np.random.PCG64(spec.seed + 7))
+    H, W = spec.Ly, spec.Lx
+    rng = np.random.Generator(np.random.PCG64(spec.seed + 7 + noise_seed))
     u = amp * u_ref(spec) * rng.uniform(-1.0, 1.0, (2, H * W))
     u[:, :W] = 0.0
     u[:, -W:] = 0.0
     return case.rho1.copy(), case.rho2.copy(), u
 
 
-def run_channels(specs_cases, inits=None, cap=100_000, chunk=WINDOW, keep_fields=False,
-                 mode=lb.LB_BATCH_LAUNCH, log=None):
+def run_channels(specs_cases, inits=None, cap=100_000, chunk=None, keep_fields=False,
+                 mode=lb.LB_BATCH_LAUNCH, log=None, st: Setup = FULL, retire=True):
     """Steps the channels (one batch) to the convergence criterion or `cap`
-    steps.  Returns per channel: steps, converged, the windowed flow-rate
-    history [(step, Q_window)], and final fields if keep_fields."""
-    params = [lb.Params.from_dict(c.params, **CONV) for _, c in specs_cases]
+    steps (to `cap` in every channel when retire is False).  Returns per
+    channel: steps, converged, the windowed flow-rate history
+    [(step, Q_window)], and final fields if keep_fields."""
+    chunk = chunk or st.window
+    conv = st.conv if retire else dict(st.conv, conv_m=2 ** 30)  # windows kept, never converged
+    params = [lb.Params.from_dict(c.params, **conv) for _, c in specs_cases]
     b = lb.Batch(params)
     for k, (_, c) in enumerate(specs_cases):
         if inits is None or inits[k] is None:
@@ -175,7 +209,7 @@ def run_channels(specs_cases, inits=None, cap=100_000, chunk=WINDOW, keep_fields
         if keep_fields:
             r["fields"] = b.fields(k)
         out.append(r)
-    lu = sum(r["steps"] for r in out) * H * W
+    lu = sum(r["steps"] * c.rho1.size for r, (_, c) in zip(out, specs_cases))
     b.close()
     return out, lu
 
@@ -204,16 +238,16 @@ def t_within(hist, q_ref: float, tol=0.01):
 
 # --- dataset and training ------------------------------------------------------
 
-def generate(seeds, cap, batch=256, log=print):
+def generate(seeds, cap, batch=256, log=print, st: Setup = FULL):
     """Plain runs to the convergence criterion; returns inputs, targets, stats."""
-    X = np.empty((len(seeds), H, W, 3), np.float32)
-    T = np.empty((len(seeds), H, W, 3), np.float32)
+    X = np.empty((len(seeds), st.H, st.W, 3), np.float32)
+    T = np.empty((len(seeds), st.H, st.W, 3), np.float32)
     stats, lu_total, t0 = [], 0, time.perf_counter()
     good = np.ones(len(seeds), bool)
     bad = []
     for s0 in range(0, len(seeds), batch):
-        sc = [make_case(s) for s in seeds[s0:s0 + batch]]
-        res, lu = run_channels(sc, cap=cap, keep_fields=True, log=log)
+        sc = [make_case(s, st) for s in seeds[s0:s0 + batch]]
+        res, lu = run_channels(sc, cap=cap, keep_fields=True, log=log, st=st)
         lu_total += lu
         for k, ((spec, case), r) in enumerate(zip(sc, res)):
             X[s0 + k] = net_input(spec, case)
@@ -235,7 +269,7 @@ def augment(X, T, rng):
     """Random periodic shift along x and mirror in y (u_y changes sign): both
     map a channel's steady state to the steady state of the transformed
     channel (walls and force are symmetric under them)."""
-    n = len(X)
+    n, H, W = X.shape[:3]
     shift = rng.integers(0, W, n)
     flip = rng.uniform(size=n) < 0.5
     cols = (np.arange(W)[None, :] - shift[:, None]) % W            # [n, W]
@@ -248,6 +282,7 @@ def augment(X, T, rng):
 
 def train(net, X, T, epochs, batch, lr, seed=0, log=print):
     rng = np.random.default_rng(seed)
+    H, W = X.shape[1:3]
     n = (len(X) // batch) * batch
     dX = ws.DeviceArray((n, H, W, 3))
     dT = ws.DeviceArray((n, H, W, 3))
@@ -283,6 +318,7 @@ def train(net, X, T, epochs, batch, lr, seed=0, log=print):
 
 
 def predict(net, X, batch):
+    H, W = X.shape[1:3]
     out = np.empty_like(X)
     dX = ws.DeviceArray((batch, H, W, 3))
     dY = ws.DeviceArray((batch, H, W, 3))
@@ -291,6 +327,8 @@ def predict(net, X, batch):
         dX.upload(X[s:s + b])
         net.forward_ptr(dX.ptr(), b, dY.ptr())
         out[s:s + b] = dY.download(b * H * W * 3).reshape(b, H, W, 3)
+    dX.free()
+    dY.free()
     return out
 
 
@@ -301,17 +339,34 @@ def _summary(ts, cap):
             "never": int(sum(t is None for t in ts))}
 
 
-def evaluate(net, seeds, cap, batch=200, log=print):
-    sc = [make_case(s) for s in seeds]
+def late_mean(hist, frac=0.5) -> float:
+    """Mean windowed flow rate over the last `frac` of a run's windows."""
+    q = [v for _, v in hist]
+    k = max(1, int(round(len(q) * frac)))
+    return float(np.mean(q[-k:]))
+
+
+def evaluate(net, seeds, cap, batch=200, log=print, st: Setup = FULL, n_ref=3):
+    """Held-out evaluation of the warm start on the steps-to-steady metric.
+
+    Every start runs `cap` steps (no early retirement).  The reference flow
+    rate of a seed, Q_ref, is robust to the run-to-run spread of the method:
+    the mean, over an ensemble of the plain start and n_ref plain starts with
+    a velocity perturbation of 1e-3 u_ref (different noise each), of each
+    run's mean windowed Q over the last half of the run; the ensemble's
+    largest deviation from Q_ref is reported as the spread.  t_1% of a start
+    is the first window end after which its windowed Q stays within 1 % of
+    Q_ref to the end of the run (None: it is not within 1 % at the end).
+    Variants: plain, warm (phase and velocity predicted), velocity only,
+    phase only."""
+    sc = [make_case(s, st) for s in seeds]
     X = np.stack([net_input(sp, c) for sp, c in sc])
     t0 = time.perf_counter()
     P = predict(net, X, 16)
     t_pred = time.perf_counter() - t0
-    # plain_perturbed: the plain start plus a velocity perturbation of 1e-3 u_ref
-    # (white noise, decays within a few steps) -- a control for how closely an
-    # equally valid start reproduces the plain run's steady flow rate
-    variants = {"plain": None, "plain_perturbed": "noise", "warm": (True, True),
-                "velocity_only": (False, True), "phase_only": (True, False)}
+    variants = {"plain": None, "warm": (True, True), "velocity_only": (False, True), "phase_only": (True, False)}
+    for k in range(n_ref):
+        variants[f"ref_{k}"] = ("noise", k)
     runs, acc = {}, []
     for name, v in variants.items():
         log(f"  eval {name}")
@@ -320,11 +375,12 @@ def evaluate(net, seeds, cap, batch=200, log=print):
             part = sc[s0:s0 + batch]
             if v is None:
                 inits = None
-            elif v == "noise":
-                inits = [perturbed_start(sp, c) for sp, c in part]
+            elif v[0] == "noise":
+                inits = [perturbed_start(sp, c, noise_seed=v[1]) for sp, c in part]
             else:
                 inits = [init_from_prediction(sp, c, P[s0 + k], *v) for k, (sp, c) in enumerate(part)]
-            r, _ = run_channels(part, inits, cap=cap, keep_fields=(v is None), log=log)
+            r, _ = run_channels(part, inits, cap=cap, keep_fields=(v is None), log=None, st=st,
+                                retire=False)
             if v is None:  # prediction accuracy against the plain end state
                 for k, (sp, c) in enumerate(part):
                     tgt = net_target(sp, *r[k].pop("fields"))
@@ -335,39 +391,41 @@ def evaluate(net, seeds, cap, batch=200, log=print):
                                 "psi_mae": float(np.abs(pr[1:-1, :, 0] - tgt[1:-1, :, 0]).mean())})
             res += r
         runs[name] = res
-    keep = [r["finite"] for r in runs["plain"]]
+    ens = ["plain"] + [f"ref_{k}" for k in range(n_ref)]
+    keep = [all(runs[e][i]["finite"] for e in ens) for i in range(len(sc))]
     excluded = [s for s, k in zip(seeds, keep) if not k]
     runs = {name: [r for r, k in zip(res, keep) if k] for name, res in runs.items()}
     acc = [a for a, k in zip(acc, keep) if k]
-    qref = [q_ref_of(r["hist"]) for r in runs["plain"]]
-    out = {"n": len(qref), "excluded_nonfinite_plain_seeds": excluded, "cap": cap,
-           "predict_seconds": t_pred, "variants": {}}
-    per_seed, seed_table = [], {}
-    for name, res in runs.items():
+    late = np.array([[late_mean(runs[e][i]["hist"]) for e in ens] for i in range(len(runs["plain"]))])
+    qref = late.mean(axis=1)
+    spread = np.abs(late / qref[:, None] - 1).max(axis=1)
+    out = {"n": len(qref), "excluded_nonfinite_seeds": excluded, "cap": cap, "n_ref": n_ref,
+           "predict_seconds": t_pred, "q_ref_spread_median": float(np.median(spread)),
+           "q_ref_spread_max": float(spread.max()), "variants": {}}
+    seed_table, t1s = {}, {}
+    for name in ["plain", "warm", "velocity_only", "phase_only"]:
+        res = runs[name]
         t1 = [t_within(r["hist"], q) for r, q in zip(res, qref)]
-        tc = [r["steps"] if r["converged"] else None for r in res]
-        qf = [q_final(r["hist"]) / q - 1 for r, q in zip(res, qref)]
+        qf = [late_mean(r["hist"]) / q - 1 for r, q in zip(res, qref)]
         fin = [abs(x) for x in qf if math.isfinite(x)]
-        out["variants"][name] = {"t1": _summary(t1, cap), "t_conv": _summary(tc, cap),
-                                 "final_Q_abs_rel_dev_median": float(np.median(fin)) if fin else None,
-                                 "final_Q_within_1pct": float(np.mean([x <= 0.01 for x in fin])) if fin else None,
+        out["variants"][name] = {"t1": _summary(t1, cap),
+                                 "late_Q_abs_rel_dev_median": float(np.median(fin)) if fin else None,
                                  "nonfinite": int(sum(not r["finite"] for r in res))}
-        per_seed.append(t1)
+        t1s[name] = t1
         seed_table[name] = {"t1": [None if t is None else int(t) for t in t1],
-                            "t_conv": [None if t is None else int(t) for t in tc],
-                            "q_final_rel": [x if math.isfinite(x) else None for x in qf]}
-    plain_t1 = per_seed[0]
-    for name, t1 in zip(runs, per_seed):
-        if name == "plain":
-            continue
-        worse = [(cap if a is None else a) > (cap if p is None else p) for a, p in zip(t1, plain_t1)]
-        ratio = [(cap if p is None else p) / max(cap if a is None else a, WINDOW) for a, p in zip(t1, plain_t1)]
-        out["variants"][name]["frac_worse_than_plain"] = float(np.mean(worse))
-        out["variants"][name]["median_speedup_t1"] = float(np.median(ratio))
+                            "late_q_rel": [x if math.isfinite(x) else None for x in qf]}
+    for name in ["warm", "velocity_only", "phase_only"]:
+        a = [cap if t is None else t for t in t1s[name]]
+        p = [cap if t is None else t for t in t1s["plain"]]
+        out["variants"][name]["frac_worse_than_plain"] = float(np.mean([x > y for x, y in zip(a, p)]))
+        out["variants"][name]["frac_better_than_plain"] = float(np.mean([x < y for x, y in zip(a, p)]))
+        out["variants"][name]["median_speedup_t1"] = float(np.median([y / max(x, st.window)
+                                                                      for x, y in zip(a, p)]))
     out["prediction"] = {k: float(np.median([a[k] for a in acc])) for k in acc[0]}
     out["prediction"]["q_pred_abs_rel_median"] = float(np.median([abs(a["q_pred_rel"]) for a in acc]))
     out["per_seed"] = seed_table
-    out["per_seed_q_ref"] = qref
+    out["per_seed_q_ref"] = qref.tolist()
+    out["per_seed_spread"] = spread.tolist()
     out["seeds"] = [s for s, k in zip(seeds, keep) if k]
     hist = {name: [[v for _, v in r["hist"]] for r in res] for name, res in runs.items()}
     return out, P, hist
@@ -387,25 +445,39 @@ def main(argv=None):
     ap.add_argument("--lb-batch", type=int, default=256, help="channels per batched LB launch")
     ap.add_argument("--out", default="gpurun_out/warmstart.json")
     ap.add_argument("--load-params", default=None, help="skip dataset and training; evaluate these weights")
+    ap.add_argument("--small", action="store_true", help="128 x 64 channels, radii halved (test scale)")
+    ap.add_argument("--n-ref", type=int, default=3, help="perturbed plain runs in the reference ensemble")
+    ap.add_argument("--g-range", type=float, nargs=2, default=None, help="pressure-gradient range")
+    ap.add_argument("--a-range", type=float, nargs=2, default=None, help="NCI-strength range")
+    ap.add_argument("--r-range", type=int, nargs=2, default=None, help="droplet-radius range")
+    ap.add_argument("--window", type=int, default=None, help="steps per flow-rate window")
     a = ap.parse_args(argv)
+    st = SMALL if a.small else FULL
+    over = {k: tuple(v) for k, v in (("G_range", a.g_range), ("A_range", a.a_range), ("R_range", a.r_range))
+            if v is not None}
+    if a.window:
+        over["window"] = a.window
+    if over:
+        st = dataclasses.replace(st, **over)
 
     def log(msg):
         print(msg, flush=True)
 
-    res = {"args": vars(a)}
+    res = {"args": vars(a), "setup": dataclasses.asdict(st)}
     t_all = time.perf_counter()
-    net = ws.UNet(ws.UNetConfig(levels=a.levels, base=a.base, cin=3, cout=3, H=H, W=W, max_batch=a.batch))
+    net = ws.UNet(ws.UNetConfig(levels=a.levels, base=a.base, cin=3, cout=3, H=st.H, W=st.W, max_batch=a.batch))
     if a.load_params:
         net.set_params(np.load(a.load_params))
         log(f"[warmstart] loaded {a.load_params}")
-        ev, _, hist = evaluate(net, list(range(5000, 5000 + a.eval)), a.cap, a.lb_batch, log)
+        ev, _, hist = evaluate(net, list(range(5000, 5000 + a.eval)), a.cap, a.lb_batch, log, st, a.n_ref)
         res["eval"] = ev
         _save(res, a.out)
         _save_hist(hist, a.out)
         log(json.dumps({"prediction": ev["prediction"], "variants": ev["variants"]}, indent=1))
         return 0
     log(f"[warmstart] dataset: {a.train} runs")
-    X, T, stats, glups, bad = generate(list(range(1000, 1000 + a.train)), a.train_cap or a.cap, a.lb_batch, log)
+    X, T, stats, glups, bad = generate(list(range(1000, 1000 + a.train)), a.train_cap or a.cap, a.lb_batch, log,
+                                       st)
     steps = np.array([s for s, _ in stats])
     res["dataset"] = {"runs": a.train, "used": int(len(X)), "nonfinite_runs": bad, "glups": glups / 1e9,
                       "steps_median": float(np.median(steps)),
@@ -418,12 +490,13 @@ def main(argv=None):
     np.save(os.path.splitext(a.out)[0] + "_params.npy", net.params())
     _save(res, a.out)
     log(f"[warmstart] evaluate on {a.eval} held-out seeds")
-    ev, _, hist = evaluate(net, list(range(5000, 5000 + a.eval)), a.cap, a.lb_batch, log)
+    ev, _, hist = evaluate(net, list(range(5000, 5000 + a.eval)), a.cap, a.lb_batch, log, st, a.n_ref)
     res["eval"] = ev
     _save_hist(hist, a.out)
     res["seconds"] = time.perf_counter() - t_all
     _save(res, a.out)
-    log(json.dumps({"prediction": ev["prediction"], "variants": ev["variants"]}, indent=1))
+    log(json.dumps({"prediction": ev["prediction"], "variants": ev["variants"],
+                    "q_ref_spread_median": ev["q_ref_spread_median"]}, indent=1))
     return 0
 
 

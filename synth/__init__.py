@@ -155,19 +155,28 @@ class ChannelSpec:
         return asdict(self)
 
 
-def channel_spec(seed: int, Lx=None, Ly=None) -> ChannelSpec:
+def channel_spec(seed: int, Lx=None, Ly=None, G_range=(1e-6, 1e-4), A_range=(0.0, 0.05),
+                 R_range=(10, 20)) -> ChannelSpec:
     """Draw one channel: Lx ~ U{256..1024}, Ly ~ U{64..160}, packing
     phi_p ~ U[0.7, 0.9], pressure gradient G_p ~ logU[1e-6, 1e-4],
-    A_nci ~ U[0, 0.05], droplet radius R ~ U{10..20}.  tau is raised so that
-    the Poiseuille peak speed 3 G_p H^2 / (8 (tau - 1/2)) stays <= 0.05, and
-    A_s = 9 sigma0 / (2 tau) keeps the surface tension at sigma0."""
+    A_nci ~ U[0, 0.05], droplet radius R ~ U{10..20} (other ranges map the
+    same draws onto them).  tau is raised so that the Poiseuille peak speed
+    3 G_p H^2 / (8 (tau - 1/2)) stays <= 0.05, and A_s = 9 sigma0 / (2 tau)
+    keeps the surface tension at sigma0."""
     rng = np.random.Generator(np.random.PCG64(seed))
     lx = int(rng.integers(256, 1025))
     ly = int(rng.integers(64, 161))
     phi_p = float(rng.uniform(0.7, 0.9))
-    G_p = float(10 ** rng.uniform(-6, -4))
-    A_nci = float(rng.uniform(0.0, 0.05))
-    R = float(rng.integers(10, 21))
+    ug = rng.uniform(-6, -4)
+    ua = rng.uniform(0.0, 0.05)
+    ur = int(rng.integers(10, 21))
+    if tuple(G_range) == (1e-6, 1e-4):
+        G_p = float(10 ** ug)
+    else:
+        lg = math.log10(G_range[0]), math.log10(G_range[1])
+        G_p = float(10 ** (lg[0] + (lg[1] - lg[0]) * (ug + 6) / 2))
+    A_nci = float(ua) if tuple(A_range) == (0.0, 0.05) else float(A_range[0] + (A_range[1] - A_range[0]) * ua / 0.05)
+    R = float(R_range[0] + (ur - 10) * (R_range[1] - R_range[0]) // 10)
     Lx = lx if Lx is None else Lx
     Ly = ly if Ly is None else Ly
     H = Ly - 2
