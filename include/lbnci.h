@@ -198,6 +198,22 @@ int lb_observables(lb_handle *h, lb_obs *out);
  * u = (j + F/2)/rho (dim*N doubles), F the force of the next collision. */
 int lb_get_fields(lb_handle *h, double *rho1, double *rho2, double *u);
 
+/* Allocation-free variant of lb_get_fields, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same outputs, bit for bit, as lb_get_fields; the
+ * device staging of the FP64 fields goes through a fixed array of
+ * LB_STATIC_SCRATCH_BYTES that each GPU the library runs on holds for the
+ * life of the process, so no hipMalloc/hipFree or allocating library call is
+ * made.  Limit: (2 + dim) * N doubles must fit, i.e. N <= 2^21 nodes in 2-D
+ * and N <= 1,677,721 in 3-D (larger lattices: LB_EINVAL, nothing run).  The
+ * handle's device must be current (LB_EINVAL otherwise).  Every call on one
+ * GPU shares that GPU's array and leaves its contents behind; calls that
+ * overlap on one GPU (other threads, or handles on other streams) race and
+ * must be serialised by the caller.  Synchronises the handle's stream.
+ * Errors: LB_EINVAL, LB_ESTATE before initialisation, LB_EDEVICE. */
+#define LB_STATIC_SCRATCH_BYTES (64u << 20)
+int lb_get_fields_static(lb_handle *h, double *rho1, double *rho2, double *u);
+
 /* Current post-streaming populations f1, f2 ([i][n], Q*N doubles each),
  * rebuilt from the stored state. */
 int lb_get_populations(lb_handle *h, double *f1, double *f2);

@@ -257,6 +257,10 @@ int lb_create(const lb_params *p, void *hip_stream, lb_handle **out) {
   if (h->D == 2) fill_tables<2>(h); else fill_tables<3>(h);
   h->N = (int64_t)p->nx * p->ny * p->nz;
   h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(LB_EDEVICE, "hipGetDevice failed");
+  }
   h->store = p->storage;
   h->s_elem = (p->storage == LB_STORE_FP16_DEV || p->storage == LB_STORE_BF16_DEV) ? 2 : 4;
   h->r_elem = (p->storage == LB_STORE_FP32) ? 8 : 4;

@@ -66,6 +66,7 @@ struct lb_handle {
   int D, Q;
   int64_t N;
   hipStream_t stream;
+  int device = 0;    // HIP device current at lb_create
   int store;         // lb_storage
   size_t s_elem;     // bytes per stored s value
   size_t r_elem;     // bytes per compute-type value (a, psi)

@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH):
         "lb_graphs": ([vp], C.c_int),
         "lb_observables": ([vp, P(lb_obs)], C.c_int),
         "lb_get_fields": ([vp, dp, dp, dp], C.c_int),
+        "lb_get_fields_static": ([vp, dp, dp, dp], C.c_int),
         "lb_get_populations": ([vp, dp, dp], C.c_int),
         "lb_get_nci": ([vp, dp, dp, ip], C.c_int),
         "lb_destroy": ([vp], None),
