@@ -141,8 +141,12 @@ typedef struct {
   int32_t flags;
 } lb_obs;
 
-/* Creates a lattice on the current HIP device.  hip_stream: a hipStream_t
- * (NULL = default stream) on which all work of the handle is enqueued.
+/* Creates a lattice on the current HIP device with the model parameters of
+ * Materials and Methods (lattice of Eq. CGLBE, relaxation time, perturbation
+ * amplitude, recolouring parameter, NCI strength and range of Eq. near_c,
+ * body force).  hip_stream: a hipStream_t (NULL = default stream) on which
+ * all work of the handle is enqueued.  *out receives the handle, which the
+ * caller releases with lb_destroy.
  * Errors: LB_EINVAL (tau <= 1/2, beta outside [0,1], sizes <= 0, nz != 1 with
  * D2Q9, walls with ny < 3, h_min > h_max, h_max > 4 or h_min <= 0, A_nci < 0,
  * unknown storage, more than 2^29 nodes), LB_ENOMEM, LB_EDEVICE.  Device
@@ -152,15 +156,18 @@ typedef struct {
  * until the first lb_step has consumed them). */
 int lb_create(const lb_params *p, void *hip_stream, lb_handle **out);
 
-/* Initial state f_i^k(x,0) = E_i(rho^k(x), u(x)) with the second-order
- * equilibrium, computed on the host in FP64.  rho1, rho2: N doubles each;
+/* Initial state of the two population sets of Eq. CGLBE,
+ * f_i^k(x,0) = E_i(rho^k(x), u(x)) with the second-order equilibrium,
+ * computed on the host in FP64.  rho1, rho2: N doubles each;
  * u: dim*N doubles (u_x block, u_y block[, u_z block]) or NULL for rest.
  * Errors: LB_EINVAL on negative/NaN densities or rho1+rho2 <= 0 at a fluid
  * node.  Resets the step counter and the convergence state. */
 int lb_init_fields(lb_handle *h, const double *rho1, const double *rho2, const double *u);
 
-/* Arbitrary initial state: f1, f2 hold Q*N doubles each in layout [i][n]
- * with the direction order of lb_lattice_tables.  Errors as lb_init_fields. */
+/* Arbitrary initial state of the two population sets of Eq. CGLBE: f1, f2
+ * hold Q*N doubles each in layout [i][n] with the direction order of
+ * lb_lattice_tables (caller-owned, copied).  Errors as lb_init_fields, and
+ * LB_EINVAL on a non-finite population. */
 int lb_set_populations(lb_handle *h, const double *f1, const double *f2);
 
 /* Advance n >= 0 steps of Eq. CGLBE (collide, then pull-stream; one step is
@@ -189,13 +196,18 @@ int lb_step_timed(lb_handle *h, int64_t n, double *ms);
  * (plain launches from then on; the results are identical either way). */
 int lb_graphs(const lb_handle *h);
 
-/* Observables of the current state (synchronises the stream).
+/* Observables of the current state (synchronises the stream): component
+ * masses and momentum (moments paragraph of Materials and Methods), flow
+ * rate Q and dispersed flow rate Q_d (the paper's observable, Results /
+ * Fig. 3), umax, and the windowed convergence state.
  * Returns LB_ENUMERIC if a NaN/Inf or a mass drift was flagged (out is still
  * filled). */
 int lb_observables(lb_handle *h, lb_obs *out);
 
-/* Current fields: rho1, rho2 (N doubles each) and the physical velocity
- * u = (j + F/2)/rho (dim*N doubles), F the force of the next collision. */
+/* Current fields: the component densities rho1, rho2 (N doubles each) and
+ * the physical velocity of the exact difference method u = (j + F/2)/rho
+ * (dim*N doubles), F the force of the next collision.  Host arrays,
+ * caller-owned; synchronises the stream.  LB_ESTATE before initialisation. */
 int lb_get_fields(lb_handle *h, double *rho1, double *rho2, double *u);
 
 /* Allocation-free variant of lb_get_fields, for callers that cannot allocate
@@ -214,19 +226,24 @@ int lb_get_fields(lb_handle *h, double *rho1, double *rho2, double *u);
 #define LB_STATIC_SCRATCH_BYTES (64u << 20)
 int lb_get_fields_static(lb_handle *h, double *rho1, double *rho2, double *u);
 
-/* Current post-streaming populations f1, f2 ([i][n], Q*N doubles each),
- * rebuilt from the stored state. */
+/* Current post-streaming populations of Eq. CGLBE, f1, f2 ([i][n], Q*N
+ * doubles each, caller-owned host arrays), rebuilt from the stored state;
+ * synchronises the stream. */
 int lb_get_populations(lb_handle *h, double *f1, double *f2);
 
 /* Per-node diagnostics of the current state: psi (N doubles; wall rows hold
- * the copied value), F_rep (dim*N doubles) and the NCI hit distance h
- * (N int32, 0 = no hit).  Any pointer may be NULL. */
+ * the copied value), the near-contact force F_rep of Eq. near_c (dim*N
+ * doubles) and the probe's hit distance h (N int32, 0 = no hit).  Any
+ * pointer may be NULL; synchronises the stream. */
 int lb_get_nci(lb_handle *h, double *psi, double *frep, int32_t *hit);
 
+/* Releases the handle and its device memory (waits for its stream first);
+ * NULL is ignored. */
 void lb_destroy(lb_handle *h);
 
-/* Lattice tables of the library's direction order: c[Q*3] (x,y,z), w[Q].
- * Returns Q, or LB_EINVAL for an unknown lattice. */
+/* Lattice tables (D2Q9, or the D3Q27 lattice of Materials and Methods) in the
+ * library's direction order: c[Q*3] (x,y,z), w[Q]; either pointer may be
+ * NULL.  Returns Q, or LB_EINVAL for an unknown lattice. */
 int lb_lattice_tables(int32_t lattice, int32_t *c, double *w);
 
 /* Step counter of the handle (number of completed lb_step steps). */
