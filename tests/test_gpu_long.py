@@ -5,10 +5,15 @@
   must match the FP64 oracle's within 1 %.
 * The 3-D benchmark channel (256 x 64 x 64, 272 droplets): FP32 storage
   against the oracle after 200 steps at the 1e-5 bar; FP16 and BF16
-  deviation storage measured against the same oracle run.
-* The same channel over 10,000 steps: time-averaged Q and Q_d of the FP16 and
-  BF16 paths against the FP32 path (the oracle-matched reference for runs
-  the oracle cannot do in test time), and the component mass drift."""
+  deviation storage against the same oracle run, within their stated error
+  budgets.
+* The same channel over 10,000 steps: time-averaged Q and Q_d over steps
+  5,000-10,000 of the FP32, FP16 and BF16 paths against the FP64 oracle's
+  (stored in tests/golden/channel3d_long.json by the oracle-only script
+  tests/golden/make_channel3d_long.py), and the component mass drift."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -60,10 +65,12 @@ def config2_oracle_200():
     return case, o
 
 
-@pytest.mark.parametrize("storage,tol_rho,tol_u", [("fp32", 1e-5, 1e-5), ("fp16", 2e-3, 0.2),
-                                                   ("bf16", 2e-2, 1.0)])
+# error budgets of the 16-bit paths: about three times the errors measured
+# on this workload (FP16: rho 1.4e-5, u 1.1e-3; BF16: rho 6.4e-5, u 2.1e-2)
+@pytest.mark.parametrize("storage,tol_rho,tol_u", [("fp32", 1e-5, 1e-5), ("fp16", 4.2e-5, 3.3e-3),
+                                                   ("bf16", 2e-4, 6.3e-2)])
 def test_full_size_200_steps(config2_oracle_200, storage, tol_rho, tol_u):
-    """FP32: the parity bar.  FP16/BF16: measured, bounds are the error budget."""
+    """FP32: the parity bar.  FP16/BF16: within the stated error budget."""
     case, o = config2_oracle_200
     g = P.Lattice(P.Params.from_dict(case.params, storage=P.STORAGE[storage]))
     g.init_fields(case.rho1, case.rho2, case.u)
@@ -75,27 +82,40 @@ def test_full_size_200_steps(config2_oracle_200, storage, tol_rho, tol_u):
     assert e["rho1"] <= tol_rho and e["rho2"] <= tol_rho and e["u"] <= tol_u
 
 
-def test_full_size_time_averaged_flow_rate_reduced_precision():
+GOLD_LONG = os.path.join(os.path.dirname(__file__), "golden", "channel3d_long.json")
+
+# budgets for the time-averaged flow rates against the oracle over steps
+# 5,000-10,000: the 1 % bar for FP32 (measured 8.8e-9); 16-bit storage within
+# about three times its measured error (FP16 3.3e-4, BF16 1.7e-2)
+LONG_TOL = {"fp32": 1e-2, "fp16": 1e-3, "bf16": 5.2e-2}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_full_size_time_averaged_flow_rate_vs_oracle(storage):
+    ref = json.load(open(GOLD_LONG))
     case = synth.hex_channel_3d()
-    say("[gpu] 3-D benchmark channel, 10k steps, FP32 / FP16 / BF16")
-    res = {}
-    for st in ("fp32", "fp16", "bf16"):
-        g = P.Lattice(P.Params.from_dict(case.params, storage=P.STORAGE[st]))
-        g.init_fields(case.rho1, case.rho2, case.u)
-        m0 = g.observables()["mass"]
-        q, qd = [], []
-        for k in range(100):
-            g.step(100)
-            if k >= 19:  # from step 2000 on
-                ob = g.observables()
-                q.append(ob["Q"]); qd.append(ob["Q_d"])
-        m1 = g.observables()["mass"]
-        res[st] = (np.mean(q), np.mean(qd), (m1 - m0) / m0)
-        g.close()
-    for st in ("fp16", "bf16"):
-        rq = abs(res[st][0] - res["fp32"][0]) / abs(res["fp32"][0])
-        rqd = abs(res[st][1] - res["fp32"][1]) / abs(res["fp32"][1])
-        say(f"  {st}: <Q> rel {rq:.2e}, <Q_d> rel {rqd:.2e}, mass drift {res[st][2]}")
-        assert rq <= 2e-2 and rqd <= 2e-2
-    say(f"  fp32: <Q> {res['fp32'][0]:.6e} <Q_d> {res['fp32'][1]:.6e} mass drift {res['fp32'][2]}")
-    assert abs(res["fp32"][2][0]) <= 1e-10
+    say(f"[gpu] 3-D benchmark channel, 10k steps, {storage}, vs the oracle's stored flow rates")
+    g = P.Lattice(P.Params.from_dict(case.params, storage=P.STORAGE[storage]))
+    g.init_fields(case.rho1, case.rho2, case.u)
+    m0 = g.observables()["mass"]
+    g.step(ref["t0"])
+    q, qd = [], []
+    while True:
+        ob = g.observables()
+        q.append(ob["Q"]); qd.append(ob["Q_d"])
+        if g.t >= ref["t1"]:
+            break
+        g.step(ref["every"])
+    m1 = g.observables()["mass"]
+    assert len(q) == len(ref["Q"])
+    rq = abs(np.mean(q) - ref["Q_mean"]) / abs(ref["Q_mean"])
+    rqd = abs(np.mean(qd) - ref["Q_d_mean"]) / abs(ref["Q_d_mean"])
+    inst = np.abs(np.array(q) - np.array(ref["Q"])).max() / np.abs(ref["Q"]).max()
+    drift = (m1 - m0) / m0
+    say(f"  {storage}: <Q> {np.mean(q):.6e} oracle {ref['Q_mean']:.6e} rel {rq:.2e}; <Q_d> rel {rqd:.2e}; "
+        f"max instantaneous rel {inst:.2e}; mass drift {drift}")
+    assert rq <= LONG_TOL[storage] and rqd <= LONG_TOL[storage]
+    if storage == "fp32":
+        assert abs(drift[0]) <= 1e-10
+    else:
+        assert np.abs(drift).max() <= 2e-4
