@@ -357,11 +357,19 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
     auto fill = [&](auto wrap) {
       R va[IT];
       float vb[IT][D];
+      // tile coordinates of element k = tid + m NT, advanced by NT per step
+      int lx = tid % PX, ly = (tid / PX) % PY, lz = tid / (PX * PY);
 #pragma unroll
       for (int m = 0; m < IT; ++m) {
         const int k = tid + m * NT;
+        if (m > 0) {
+          lx += NT % PX;
+          ly += (NT / PX) % PY;
+          lz += NT / (PX * PY);
+          if (lx >= PX) { lx -= PX; ++ly; }
+          if (ly >= PY) { ly -= PY; ++lz; }
+        }
         if (k < TS) {
-          const int lx = k % PX, ly = (k / PX) % PY, lz = k / (PX * PY);
           const int gxx = wrap(x0 + lx - 1, A.nx);
           const int gyy = wrap(y0 + ly - 1, A.ny);
           const int gzz = (D == 3) ? wrap(z0 + lz - 1, A.nz) : 0;
@@ -516,11 +524,20 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
     constexpr int FILL = LX * LY * LZ, IT = (FILL + NT - 1) / NT;
     auto fill = [&](auto wrap) {
       R v[IT];
+      // tile coordinates of element k = tid + m NT, advanced by NT per step
+      // (no division in the loop)
+      int lx = tid % LX, ly = (tid / LX) % LY, lz = tid / (LX * LY);
 #pragma unroll
       for (int m = 0; m < IT; ++m) {
         const int k = tid + m * NT;
+        if (m > 0) {
+          lx += NT % LX;
+          ly += (NT / LX) % LY;
+          lz += NT / (LX * LY);
+          if (lx >= LX) { lx -= LX; ++ly; }
+          if (ly >= LY) { ly -= LY; ++lz; }
+        }
         if (k < FILL) {
-          const int lx = k % LX, ly = (k / LX) % LY, lz = k / (LX * LY);
           const int gxx = wrap(x0 + lx - H, A.nx);
           int gyy = y0 + ly - H;
           if (A.walls) gyy = gyy < 1 ? 1 : (gyy > A.ny - 2 ? A.ny - 2 : gyy);
@@ -576,6 +593,11 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
     // near-contact probe along n = -G^: first s with psi(x + round(s n)) >= psi(x)
     R Fr[3] = {0, 0, 0};
     int hit = 0;
+    // probe samples lie within ceil(h_max) <= 4 nodes of x, so on lattices at
+    // least that long in every direction a coordinate wraps by one period at
+    // most (a block-uniform test; integer modulo otherwise)
+    const bool wrap1 = A.nx >= A.smaxc + 1 && A.ny >= A.smaxc + 1 && (D == 2 || A.nz >= A.smaxc + 1);
+    auto wrapp = [&](int v, int n) { return wrap1 ? wrap_near(v, n) : wrapi(v, n); };
     if (NCI == 1 && A.A > (R)0 && g > (R)0) {
       // continuous-NCI variant: psi at x + s n by multilinear interpolation
       // (lerp x, then y, then z), h at the linear crossing between samples
@@ -584,11 +606,11 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       const R nn[3] = {-Gh[0], -Gh[1], -Gh[2]};
       auto node_psi = [&](int ox, int oy, int oz) -> R {
         if (abs(ox) <= H && abs(oy) <= H && abs(oz) <= H) return T(ox, oy, oz);
-        const int xt = wrapi(x + ox, A.nx);
+        const int xt = wrapp(x + ox, A.nx);
         int yt = y + oy;
         if (A.walls) yt = yt < 1 ? 1 : (yt > A.ny - 2 ? A.ny - 2 : yt);
-        else yt = wrapi(yt, A.ny);
-        const int zt = (D == 3) ? wrapi(z + oz, A.nz) : 0;
+        else yt = wrapp(yt, A.ny);
+        const int zt = (D == 3) ? wrapp(z + oz, A.nz) : 0;
         return ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)yt + (uint32_t)A.ny * zt));
       };
       R prev = ps, hc = 0;
@@ -648,9 +670,9 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         } else if (abs(ox) <= H && abs(oy) <= H && abs(oz) <= H) {
           pv = T(ox, oy, oz);
         } else {
-          const int xt = wrapi(x + ox, A.nx);
-          const int ytt = A.walls ? yt : wrapi(yt, A.ny);
-          const int zt = (D == 3) ? wrapi(z + oz, A.nz) : 0;
+          const int xt = wrapp(x + ox, A.nx);
+          const int ytt = A.walls ? yt : wrapp(yt, A.ny);
+          const int zt = (D == 3) ? wrapp(z + oz, A.nz) : 0;
           pv = ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)ytt + (uint32_t)A.ny * zt));
         }
         if (pv >= ps) { hit = s; break; }
