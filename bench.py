@@ -147,6 +147,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="channel3d", choices=["channel3d", "sweep", "unet", "analysis", "geometry",
                                                           "focuser", "oracle"])
     ap.add_argument("--batch", type=int, default=16, help="U-Net training batch (--workload unet)")
+    ap.add_argument("--conv-algo", type=int, default=0, choices=[0, 1],
+                    help="U-Net 3x3 convolutions: 0 direct kernels where the shape allows, 1 implicit GEMM only")
     ap.add_argument("--mode", default="auto", choices=["auto", "persistent", "launch"],
                     help="batched sweep: the autotuner's choice, or a fixed mode")
     a = ap.parse_args(argv)
@@ -344,7 +346,7 @@ def bench_unet(a):
     import synth
     from paper_2003_11069_amd import ws
     B, Hh, Ww = a.batch, 128, 256
-    net = ws.UNet(ws.UNetConfig(levels=4, base=32, cin=3, cout=3, H=Hh, W=Ww, max_batch=B))
+    net = ws.UNet(ws.UNetConfig(levels=4, base=32, cin=3, cout=3, H=Hh, W=Ww, max_batch=B, conv_algo=a.conv_algo))
     net.set_params(synth.unet_params(4, 32, seed=1))
     x, t = synth.unet_batch(B, Hh, Ww, 3, 3, seed=2)
     dx, dt = ws.DeviceArray.from_host(x), ws.DeviceArray.from_host(t)
@@ -363,7 +365,8 @@ def bench_unet(a):
            "ms_per_step": round(el / a.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "bf16", "data": "synthetic (seeded smooth fields)",
            "config": {"workload": "U-Net 4 levels, base 32, 3x128x256 -> 3x128x256, MSE + Adam",
-                      "batch": B, "params": net.n_params, "gflop_per_sample_fwd": round(fwd / B / 1e9, 3)},
+                      "batch": B, "params": net.n_params, "gflop_per_sample_fwd": round(fwd / B / 1e9, 3),
+                      "conv_algo": ["direct 3x3 where the shape allows", "implicit GEMM"][a.conv_algo]},
            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
                         "frac": round(tflops / 2500.0, 4), "traffic": None}}
     print(json.dumps(out), flush=True)

@@ -81,6 +81,13 @@ typedef struct {
   int32_t H, W;      /* image size; divisible by 2^(L-1), and the lowest
                         level H W / 4^(L-1) a multiple of 64 pixels           */
   int32_t max_batch; /* largest batch passed to forward/backward             */
+  int32_t conv_algo; /* 3x3 convolutions: 0 = direct kernels (an LDS-staged
+                        8 x 32 pixel tile and its halo serve all nine taps)
+                        at every level whose image is a whole number of such
+                        tiles and whose channel counts are multiples of 32,
+                        implicit GEMM elsewhere; 1 = implicit GEMM only.
+                        Both give the same results up to FP32 summation
+                        order.                                              */
 } ws_config;
 
 /* Allocates the network (parameters zero until ws_set_params). */

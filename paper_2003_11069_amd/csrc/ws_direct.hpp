@@ -1,0 +1,506 @@
+// ws_direct.hpp -- direct 3x3 convolutions (stride 1, zero padding 1) of the
+// warm-start U-Net on v_mfma_f32_16x16x32_bf16, for images whose width is a
+// multiple of 32 and height a multiple of 8.
+//
+// A block owns one 8 x 32 pixel tile of one image.  It stages the tile and
+// its one-pixel halo in LDS once per 32-channel slice and reads all nine taps
+// from there (the implicit GEMM of ws_kernels.hpp gathers every tap from
+// global memory, and converts a backward operand once per tap).
+//
+//   k_dconv   forward (BF16 input; bias, ReLU, BF16 output) and backward-data
+//             (output gradient times the ReLU mask, rounded to BF16 while
+//             staging; FP32 output, stored or added).  The staged operand has
+//             Kc channels (a multiple of 32, or the 8 of the padded network
+//             input), the output Nc (a multiple of 32).  Weights [Nc][9][Kc]:
+//             the forward W, or for backward-data its flipped transpose.
+//   k_dwgrad  weight and bias gradient.  Both operands are staged transposed
+//             (pixels contiguous, the reduction dimension of the MFMA); the
+//             input window of taps kx = 1, 2 is the staged row shifted by one
+//             or two pixels in registers.  A block sums a run of tiles and
+//             writes partial sums [split][Cout][9 Cin + 1] (bias last).
+//   k_wreduce sums the partials over splits in a fixed order.
+//
+// Lane layout of the MFMA (as in ws_kernels.hpp): lane l holds
+// A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16] and receives
+// D[4(l/16)+r][l%16], r = 0..3.
+#pragma once
+#include "ws_kernels.hpp"
+
+namespace wsk {
+
+constexpr int DT_H = 8, DT_W = 32;           // pixel tile of a block
+constexpr int DH = DT_H + 2, DW = DT_W + 2;  // with the halo
+constexpr int DP = 40;                       // LDS pitch (bf16) of one pixel's 32-channel slice: 80 B
+
+// Tiles of a batch of images: tile t = (b, row band, column band), column band fastest.
+struct DTiles {
+  int tx, ty, n;
+  static DTiles make(int B, int H, int W) { return DTiles{W / DT_W, H / DT_H, B * (H / DT_H) * (W / DT_W)}; }
+  __device__ __forceinline__ void at(int t, int &b, int &y0, int &x0) const {
+    const int xi = t % tx;
+    t /= tx;
+    const int yi = t % ty;
+    b = t / ty;
+    y0 = yi * DT_H;
+    x0 = xi * DT_W;
+  }
+};
+
+// Workgroups are dealt round-robin to the eight XCDs; give each XCD a run of
+// consecutive tiles so that neighbouring tiles' halos meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n) { return n % 8 ? bid : (bid % 8) * (n / 8) + bid / 8; }
+
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+__device__ __forceinline__ uint32_t pack_bf16(bf16 lo, bf16 hi) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+}
+
+// ---------------------------------------------------------------------------
+struct DConv {
+  Img g;
+  DTiles T;
+  int tpb;               // tiles per block (block b runs tiles b tpb ..)
+  View<const bf16> x;    // forward: input activations (Kc channels)
+  View<const float> dx;  // backward-data: output gradient of the layer (Kc channels)
+  View<const bf16> act;  // backward-data: the layer's output (ReLU mask)
+  int Kc, Nc;
+  const bf16 *Wk;        // [Nc][9][Kc]
+  const float *bias;     // forward
+  View<bf16> y;          // forward output (Nc channels)
+  View<float> dy;        // backward-data output
+  int accumulate;        // backward-data: add to dy
+};
+
+// Block: a run of tpb tiles x 32 NW output channels (blockIdx.y), 4 NW
+// waves.  Wave w computes rows 2 (w % 4), 2 (w % 4) + 1 of a tile (four
+// 16-pixel M tiles) for output channels 32 (w / 4) .. + 31 (two N tiles);
+// several N groups in one block share each staged input tile.  The block
+// walks (tile, 32-channel slice) items; the global loads of item i + 1 are
+// issued before the MFMAs of item i and land in registers, all of an item's
+// loads together, so memory latency overlaps the MFMAs.
+template <bool BWD, bool C8, int NW>
+__global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
+  constexpr int NT = 2, BN = 32 * NW, NTH = 256 * NW;
+  constexpr int XP = C8 ? 8 : DP;  // the padded input has one 8-channel chunk per pixel
+  constexpr int NWS = C8 ? 3 : 9;  // weight stages per slice: 4-tap groups, or taps
+  constexpr int CPP = C8 ? 1 : 4;  // 8-channel chunks per staged pixel
+  constexpr int XN = DH * DW * CPP, XIT = (XN + NTH - 1) / NTH;
+  constexpr int WN = NWS * BN * 4, WIT = (WN + NTH - 1) / NTH;
+  constexpr int OP = 32 + 8;  // pixel pitch of the forward output staged through Xs (NW = 1)
+  constexpr int XS = (NW > 1 || DH * DW * XP > 4 * 64 * OP) ? DH * DW * XP : 4 * 64 * OP;
+  __shared__ __attribute__((aligned(16))) bf16 Xs[XS];
+  __shared__ __attribute__((aligned(16))) bf16 Ws[NWS * BN * DP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  const int rg = wave & 3, ng = wave >> 2;  // row pair, N group
+  const int n0 = blockIdx.y * BN, nw0 = n0 + 32 * ng, H = P.g.H, W = P.g.W;
+  const int slices = C8 ? 1 : P.Kc / 32;
+  const int blk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int t0 = blk * P.tpb, t1 = min(P.T.n, t0 + P.tpb);
+  const int items = (t1 - t0) * slices;
+  f4 acc[4][NT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  // staging registers (BF16; a backward item's loads are all issued before
+  // the first is converted, so they are in flight together)
+  bf16x8 xa[XIT], wr[WIT];
+  float bias[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) bias[j] = BWD ? 0.f : P.bias[nw0 + 16 * j + l16];
+  // per-thread staging geometry, fixed for every tile: halo row and column of
+  // each item and its element offset from the tile's first pixel
+  int srr[XIT], scc[XIT], soff[XIT], aoff[XIT];
+#pragma unroll
+  for (int it = 0; it < XIT; ++it) {
+    const int q = tid + NTH * it;
+    const int pix = q / CPP, ch = (q - pix * CPP) * 8;
+    srr[it] = q < XN ? pix / DW : -1000;  // -1000: past the tile, never staged
+    scc[it] = pix - (pix / DW) * DW;
+    const int rel = (srr[it] - 1) * W + scc[it] - 1;
+    soff[it] = rel * (BWD ? P.dx.cs : P.x.cs) + ch;
+    aoff[it] = BWD ? rel * P.act.cs + ch : 0;
+  }
+  auto gload = [&](int item) {
+    float4 xg[BWD ? XIT : 1][2];
+    const int t = t0 + item / slices, s = item % slices;
+    int b, y0, x0;
+    P.T.at(t, b, y0, x0);
+    const int64_t tb = (int64_t)(b * H + y0) * W + x0;  // the tile's first pixel
+    const bf16 *xb = P.x.p + tb * P.x.cs + P.x.coff + s * 32;
+    const float *db = P.dx.p + tb * P.dx.cs + P.dx.coff + s * 32;
+    const bf16 *ab = P.act.p + tb * P.act.cs + P.act.coff + s * 32;
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int yy = y0 + srr[it] - 1, xx = x0 + scc[it] - 1;
+      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      if (BWD) {
+        xg[it][0] = xg[it][1] = float4{0.f, 0.f, 0.f, 0.f};
+        xa[it] = zero8();
+        if (in) {
+          const float4 *d = reinterpret_cast<const float4 *>(db + soff[it]);
+          xg[it][0] = d[0];
+          xg[it][1] = d[1];
+          xa[it] = *reinterpret_cast<const bf16x8 *>(ab + aoff[it]);
+        }
+      } else {
+        xa[it] = in ? *reinterpret_cast<const bf16x8 *>(xb + soff[it]) : zero8();
+      }
+    }
+    if (BWD) {  // output gradient times the ReLU mask, rounded to BF16
+#pragma unroll
+      for (int it = 0; it < XIT; ++it) {
+        const float f[8] = {xg[it][0].x, xg[it][0].y, xg[it][0].z, xg[it][0].w,
+                            xg[it][1].x, xg[it][1].y, xg[it][1].z, xg[it][1].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xa[it][j] = (bf16)((float)xa[it][j] > 0.f ? f[j] : 0.f);
+      }
+    }
+    if (slices == 1 && item > 0) return;  // one slice: the weights stay in LDS
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) {
+      const int q = tid + NTH * it;
+      const int gq = q & 3, n = (q >> 2) % BN, w = (q >> 2) / BN;
+      wr[it] = zero8();
+      if (q < WN) {
+        if (C8) {  // k = 8 gq + ci of stage w is tap 4 w + gq
+          const int tap = 4 * w + gq;
+          if (tap < 9) wr[it] = *reinterpret_cast<const bf16x8 *>(P.Wk + ((size_t)(n0 + n) * 9 + tap) * 8);
+        } else {
+          wr[it] = *reinterpret_cast<const bf16x8 *>(P.Wk + ((size_t)(n0 + n) * 9 + w) * P.Kc + s * 32 + 8 * gq);
+        }
+      }
+    }
+  };
+  auto lstore = [&](int item) {
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int q = tid + NTH * it;
+      if (q < XN) {
+        const int pix = q / CPP, ch = (q - pix * CPP) * 8;
+        *reinterpret_cast<bf16x8 *>(&Xs[pix * XP + ch]) = xa[it];
+      }
+    }
+    if (slices == 1 && item > 0) return;
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) {
+      const int q = tid + NTH * it;
+      if (q < WN) {
+        const int gq = q & 3, n = (q >> 2) % BN, w = (q >> 2) / BN;
+        *reinterpret_cast<bf16x8 *>(&Ws[(w * BN + n) * DP + 8 * gq]) = wr[it];
+      }
+    }
+  };
+  if (items > 0) gload(0);
+  for (int item = 0; item < items; ++item) {
+    if (item) __syncthreads();  // the previous item's reads are done
+    lstore(item);
+    __syncthreads();
+    if (item + 1 < items) gload(item + 1);
+#pragma unroll
+    for (int w = 0; w < NWS; ++w) {
+      int ky, kx;
+      bool ok = true;
+      if (C8) {
+        const int tap = 4 * w + g;
+        ok = tap < 9;
+        ky = tap / 3;
+        kx = tap - 3 * ky;
+      } else {
+        ky = w / 3;
+        kx = w - 3 * ky;
+      }
+      bf16x8 bw[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        bw[j] = *reinterpret_cast<const bf16x8 *>(&Ws[(w * BN + 32 * ng + 16 * j + l16) * DP + 8 * g]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 2 * rg + (i >> 1), col = 16 * (i & 1) + l16;
+        bf16x8 a;
+        if (C8) a = ok ? *reinterpret_cast<const bf16x8 *>(&Xs[((row + ky) * DW + col + kx) * 8]) : zero8();
+        else a = *reinterpret_cast<const bf16x8 *>(&Xs[((row + ky) * DW + col + kx) * DP + 8 * g]);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (item % slices != slices - 1) continue;
+    // the tile's last slice: bias and ReLU (forward) and store (no loads
+    // here but the accumulating case's, which would wait for the prefetch)
+    int b, y0, x0;
+    P.T.at(t0 + item / slices, b, y0, x0);
+    if (BWD && P.accumulate) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const size_t p = (size_t)(b * H + y0 + 2 * rg + (i >> 1)) * W + x0 + 16 * (i & 1) + 4 * g + q;
+            acc[i][j][q] += P.dy.p[p * P.dy.cs + P.dy.coff + nw0 + 16 * j + l16];
+          }
+    }
+    if (BWD || NW > 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 2 * rg + (i >> 1);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int n = nw0 + 16 * j + l16;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int col = 16 * (i & 1) + 4 * g + q;
+            const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
+            if (BWD) {
+              P.dy.p[p * P.dy.cs + P.dy.coff + n] = acc[i][j][q];
+            } else {
+              const float r = acc[i][j][q] + bias[j];
+              P.y.p[p * P.y.cs + P.y.coff + n] = (bf16)(r > 0.f ? r : 0.f);
+            }
+          }
+          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    } else {
+      // BF16 results through LDS (each wave's 64 pixels x 32 channels in its
+      // own part of Xs, pixel pitch OP), then 16-byte stores
+      __syncthreads();  // every wave is done reading Xs for this item
+      bf16 *O = Xs + wave * 64 * OP;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float r = acc[i][j][q] + bias[j];
+            O[(32 * (i >> 1) + 16 * (i & 1) + 4 * g + q) * OP + 16 * j + l16] = (bf16)(r > 0.f ? r : 0.f);
+          }
+          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = lane + 64 * k, px = e / 4, c8 = (e - px * 4) * 8;
+        const int row = 2 * rg + px / 32, col = px % 32;
+        const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
+        *reinterpret_cast<bf16x8 *>(P.y.p + p * P.y.cs + P.y.coff + n0 + c8) =
+            *reinterpret_cast<const bf16x8 *>(&O[px * OP + c8]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+struct DWGrad {
+  Img g;
+  DTiles T;
+  int tps;                 // tiles per split (split z sums tiles z tps ..)
+  View<const float> dout;  // output gradient of the layer (Cout channels)
+  View<const bf16> act;    // the layer's output (ReLU mask)
+  View<const bf16> in;     // the layer's input (Cin channels)
+  int Cin, Cout;
+  float *partial;          // [splits][Cout][9 Cin + 1]
+};
+
+constexpr int WA_P = DT_H * DT_W + 8;  // co pitch (bf16) of the transposed output gradient: 528 B
+constexpr int WB_R = 40;               // row pitch of the transposed input (34 columns used)
+constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
+
+// Block (split, 32 output channels, 16 HW input channels; HW = 1 for the
+// padded network input, whose channels 8..15 are staged as zeros), 2 HW
+// waves.  Wave w: output channels 16 (w & 1), input channels 16 (w >> 1), all
+// nine taps; K = the 32 pixels of one tile row.  The output-gradient tile
+// (the FP32 operand) is staged once for all 16 HW input channels.
+template <bool C8, int HW>
+__global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
+  constexpr int CI = 16 * HW, NTH = 128 * HW;
+  __shared__ __attribute__((aligned(16))) bf16 As[32 * WA_P];  // dPre^T [co][r][c]
+  __shared__ __attribute__((aligned(16))) bf16 Bs[CI * WB_P];  // in^T [ci][rr][cc], pixel (y0+rr-1, x0+cc-1)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  const int mt = wave & 1, h = wave >> 1;
+  const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * CI;
+  const int H = P.g.H, W = P.g.W;
+  f4 acc[9], accb = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
+  const int z = blockIdx.x;
+  const int tb = z * P.tps, te = min(P.T.n, tb + P.tps);
+  // staging registers of one tile: output gradient (two pixels x 8 channels
+  // per item: FP32 values and the mask), input (two pixels x 8 channels)
+  constexpr int AN = DT_H * DT_W / 2 * 4, AIT = AN / NTH;
+  constexpr int NCH = CI / 8, BN_ = DH * (DW / 2) * NCH, BIT = (BN_ + NTH - 1) / NTH;
+  float4 ga[AIT][4];
+  bf16x8 ma[AIT][2], ib[BIT][2];
+  auto gload = [&](int t) {
+    int b, y0, x0;
+    P.T.at(t, b, y0, x0);
+#pragma unroll
+    for (int it = 0; it < AIT; ++it) {
+      const int q = tid + NTH * it;
+      const int cq = q & 3, pp = q >> 2, r = pp >> 4, c = 2 * (pp & 15);
+      const int p = (b * H + y0 + r) * W + x0 + c;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const size_t o = (size_t)(p + e);
+        const float4 *d = reinterpret_cast<const float4 *>(P.dout.p + o * P.dout.cs + P.dout.coff + co0 + 8 * cq);
+        ga[it][2 * e] = d[0];
+        ga[it][2 * e + 1] = d[1];
+        ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.act.p + o * P.act.cs + P.act.coff + co0 + 8 * cq);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < BIT; ++it) {
+      const int q = tid + NTH * it;
+      const int cq = q % NCH, pp = q / NCH, rr = pp / (DW / 2), cc = 2 * (pp - rr * (DW / 2));
+      const int yy = y0 + rr - 1, xa = x0 + cc - 1;
+      ib[it][0] = ib[it][1] = zero8();
+      if (q < BN_ && (!C8 || cq == 0) && yy >= 0 && yy < H) {
+        const bf16 *rowp = P.in.p + (size_t)(b * H + yy) * W * P.in.cs + P.in.coff + ci0 + 8 * cq;
+        if (xa >= 0) ib[it][0] = *reinterpret_cast<const bf16x8 *>(rowp + (size_t)xa * P.in.cs);
+        if (xa + 1 < W) ib[it][1] = *reinterpret_cast<const bf16x8 *>(rowp + (size_t)(xa + 1) * P.in.cs);
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int it = 0; it < AIT; ++it) {
+      const int q = tid + NTH * it;
+      const int cq = q & 3, pp = q >> 2, r = pp >> 4, c = 2 * (pp & 15);
+      bf16 v[2][8];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float f[8] = {ga[it][2 * e].x, ga[it][2 * e].y, ga[it][2 * e].z, ga[it][2 * e].w,
+                            ga[it][2 * e + 1].x, ga[it][2 * e + 1].y, ga[it][2 * e + 1].z, ga[it][2 * e + 1].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[e][j] = (bf16)((float)ma[it][e][j] > 0.f ? f[j] : 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * WA_P + r * DT_W + c]) = pack_bf16(v[0][j], v[1][j]);
+    }
+#pragma unroll
+    for (int it = 0; it < BIT; ++it) {
+      const int q = tid + NTH * it;
+      if (q < BN_) {
+        const int cq = q % NCH, pp = q / NCH, rr = pp / (DW / 2), cc = 2 * (pp - rr * (DW / 2));
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          *reinterpret_cast<uint32_t *>(&Bs[(8 * cq + j) * WB_P + rr * WB_R + cc]) = pack_bf16(ib[it][0][j], ib[it][1][j]);
+      }
+    }
+  };
+  if (tb < te) gload(tb);
+  for (int t = tb; t < te; ++t) {
+    __syncthreads();  // the previous tile's reads are done
+    lstore();
+    __syncthreads();
+    if (t + 1 < te) gload(t + 1);
+    {
+#pragma unroll 2
+      for (int r = 0; r < DT_H; ++r) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[(16 * mt + l16) * WA_P + r * DT_W + 8 * g]);
+        if (h == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, accb, 0, 0, 0);
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+          const bf16 *src = &Bs[(16 * h + l16) * WB_P + (r + ky) * WB_R + 8 * g];
+          const u32x4 lo = *reinterpret_cast<const u32x4 *>(src), hi = *reinterpret_cast<const u32x4 *>(src + 8);
+          u32x4 s1, s2;  // windows starting one and two pixels further right
+          s1[0] = __builtin_amdgcn_alignbyte(lo[1], lo[0], 2);
+          s1[1] = __builtin_amdgcn_alignbyte(lo[2], lo[1], 2);
+          s1[2] = __builtin_amdgcn_alignbyte(lo[3], lo[2], 2);
+          s1[3] = __builtin_amdgcn_alignbyte(hi[0], lo[3], 2);
+          s2[0] = lo[1];
+          s2[1] = lo[2];
+          s2[2] = lo[3];
+          s2[3] = hi[0];
+          acc[3 * ky + 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, lo), acc[3 * ky + 0], 0, 0, 0);
+          acc[3 * ky + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, s1), acc[3 * ky + 1], 0, 0, 0);
+          acc[3 * ky + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, s2), acc[3 * ky + 2], 0, 0, 0);
+        }
+      }
+    }
+  }
+  const int Kw = 9 * P.Cin;
+  const int ci = ci0 + 16 * h + l16;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int co = co0 + 16 * mt + 4 * g + q;
+    float *row = P.partial + ((size_t)z * P.Cout + co) * (Kw + 1);
+    if (ci < P.Cin) {
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) row[tap * P.Cin + ci] = acc[tap][q];
+    }
+    if (h == 0 && blockIdx.z == 0 && l16 == 0) row[Kw] = accb[q];
+  }
+}
+
+// Fixed-order sum of split partials [splits][E] (E = rows (Kw + 1), a
+// multiple of 4) into dW [rows][Kw] and db [rows] (column Kw; per-row bias
+// sums, folded by k_bias_fold where several rows share a bias).  A block sums
+// 256 consecutive elements (a float4 per lane) over 16 split groups (group
+// g adds splits g, g + 16, ... in four interleaved partial sums), then
+// combines the groups by a fixed tree.
+constexpr int WR_G = 16;
+static __global__ __launch_bounds__(64 * WR_G) void k_wreduce(const float *partial, int splits, int E, int Kw, float *dW,
+                                                            float *db) {
+  __shared__ float4 sh[WR_G][64];
+  const int lane = threadIdx.x & 63, gr = threadIdx.x >> 6;
+  const int e4 = blockIdx.x * 64 + lane, E4 = E / 4;
+  float4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
+  if (e4 < E4) {
+    const float4 *p = reinterpret_cast<const float4 *>(partial) + e4;
+    const size_t st = (size_t)E4;
+    int z = gr;
+    for (; z + 3 * WR_G < splits; z += 4 * WR_G) {
+      const float4 v0 = p[z * st], v1 = p[(z + WR_G) * st], v2 = p[(z + 2 * WR_G) * st], v3 = p[(z + 3 * WR_G) * st];
+      a0.x += v0.x; a0.y += v0.y; a0.z += v0.z; a0.w += v0.w;
+      a1.x += v1.x; a1.y += v1.y; a1.z += v1.z; a1.w += v1.w;
+      a2.x += v2.x; a2.y += v2.y; a2.z += v2.z; a2.w += v2.w;
+      a3.x += v3.x; a3.y += v3.y; a3.z += v3.z; a3.w += v3.w;
+    }
+    for (; z < splits; z += WR_G) {
+      const float4 v = p[z * st];
+      a0.x += v.x; a0.y += v.y; a0.z += v.z; a0.w += v.w;
+    }
+  }
+  float4 s;
+  s.x = (a0.x + a1.x) + (a2.x + a3.x);
+  s.y = (a0.y + a1.y) + (a2.y + a3.y);
+  s.z = (a0.z + a1.z) + (a2.z + a3.z);
+  s.w = (a0.w + a1.w) + (a2.w + a3.w);
+  sh[gr][lane] = s;
+  __syncthreads();
+  for (int w = WR_G / 2; w >= 1; w >>= 1) {
+    if (gr < w) {
+      float4 &d = sh[gr][lane];
+      const float4 o = sh[gr + w][lane];
+      d.x += o.x; d.y += o.y; d.z += o.z; d.w += o.w;
+    }
+    __syncthreads();
+  }
+  if (gr == 0 && e4 < E4) {
+    const float4 v = sh[0][lane];
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = 4 * e4 + k, m = e / (Kw + 1), c = e - m * (Kw + 1);
+      if (c < Kw) dW[(size_t)m * Kw + c] = vv[k];
+      else db[m] = vv[k];
+    }
+  }
+}
+
+// db[c] = sum over m = c, c + Cb, ... < M of rows[m], in ascending m.
+static __global__ __launch_bounds__(256) void k_bias_fold(const float *rows, int M, int Cb, float *db) {
+  for (int c = threadIdx.x; c < Cb; c += 256) {
+    float s = 0.f;
+    for (int m = c; m < M; m += Cb) s += rows[m];
+    db[c] = s;
+  }
+}
+
+}  // namespace wsk

@@ -310,7 +310,7 @@ struct ConvBwdData {
 // Backward-weight of ConvFwd, split over pixels:
 //   dW[co][k] = sum_p dPre[p, co] im2col(in)[p, k],  db[co] = sum_p dPre[p, co]
 // (the bias is column k = K of a ones column).  Reduction over pixels; split z
-// writes partial[z][co][k] (FP32), summed in fixed order by k_split_reduce.
+// writes partial[z][co][k] (FP32), summed in fixed order by k_wreduce.
 // Both operands are COL chunks (8 channels of one pixel).  TR = false: M =
 // Cout, N = K + 1; TR = true (narrow Cout): M = K + 1, N = Cout.
 template <int KS, bool RELU, bool TR = false>
@@ -469,50 +469,6 @@ struct UpBwdWeight {
   }
 };
 
-// Sums split partials [splits][M][Kw+1] in a fixed order into dW[m][k] (k < Kw)
-// and, for the ones column, db[c] = sum over rows m = c (mod Cb) of column Kw.
-// A block handles 16 output elements with 16 split groups: group g adds splits
-// g, g+16, g+32, ... (four interleaved partial sums, combined in a fixed
-// order), then the groups are combined by a fixed tree.
-constexpr int RED_E = 16, RED_G = 16;
-static __global__ __launch_bounds__(RED_E * RED_G) void k_split_reduce(const float *partial, int splits, int M,
-                                                                        int Kw, float *dW, float *db, int Cb) {
-  __shared__ float sh[RED_G][RED_E + 1];
-  const int el = threadIdx.x % RED_E, gr = threadIdx.x / RED_E;
-  const int e = blockIdx.x * RED_E + el;  // element: dW entries, then biases
-  const int Nw = Kw + 1, nW = M * Kw;
-  auto column = [&](int m, int k) {
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    int z = gr;
-    for (; z + 3 * RED_G < splits; z += 4 * RED_G) {
-      a0 += partial[((size_t)z * M + m) * Nw + k];
-      a1 += partial[((size_t)(z + RED_G) * M + m) * Nw + k];
-      a2 += partial[((size_t)(z + 2 * RED_G) * M + m) * Nw + k];
-      a3 += partial[((size_t)(z + 3 * RED_G) * M + m) * Nw + k];
-    }
-    for (; z < splits; z += RED_G) a0 += partial[((size_t)z * M + m) * Nw + k];
-    return (a0 + a1) + (a2 + a3);
-  };
-  float acc = 0.f;
-  if (e < nW) {
-    const int m = e / Kw, k = e - m * Kw;
-    acc = column(m, k);
-  } else if (e < nW + Cb) {
-    const int c = e - nW;
-    for (int m = c; m < M; m += Cb) acc += column(m, Kw);
-  }
-  sh[gr][el] = acc;
-  __syncthreads();
-  for (int w = RED_G / 2; w >= 1; w >>= 1) {
-    if (gr < w) sh[gr][el] += sh[gr + w][el];
-    __syncthreads();
-  }
-  if (gr == 0) {
-    if (e < nW) dW[e] = sh[0][el];
-    else if (e < nW + Cb) db[e - nW] = sh[0][el];
-  }
-}
-
 // ---------------------------------------------------------------------------
 // 2x2 max pooling (stride 2): forward on BF16, backward routes the gradient to
 // the first maximum in the order (0,0), (0,1), (1,0), (1,1) and adds it to the
@@ -582,17 +538,27 @@ static __global__ __launch_bounds__(256) void k_mse(const float *y, int cs, cons
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-static __global__ __launch_bounds__(256) void k_sum_partials(const double *partial, int n, double scale, double *out) {
-  __shared__ double sh[256];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < n; k += 256) s += partial[k];
-  sh[threadIdx.x] = s;
+// One block of 1024 threads: thread t adds partials t, t + 1024, ... in four
+// interleaved sums (loads in flight together), then a fixed tree.
+static __global__ __launch_bounds__(1024) void k_sum_partials(const double *partial, int n, double scale, double *out) {
+  __shared__ double sh[1024];
+  const int t = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = t;
+  for (; k + 3 * 1024 < n; k += 4 * 1024) {
+    a0 += partial[k];
+    a1 += partial[k + 1024];
+    a2 += partial[k + 2 * 1024];
+    a3 += partial[k + 3 * 1024];
+  }
+  for (; k < n; k += 1024) a0 += partial[k];
+  sh[t] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = sh[0] * scale;
+  if (t == 0) *out = sh[0] * scale;
 }
 
 // Adam (bias-corrected) on FP32 master parameters.

@@ -17,7 +17,7 @@
 //                    d2[l].W [C_l][3][3][C_l],   d2[l].b [C_l]
 //   head.W [8][C0], head.b [8]
 #include "wsnet.h"
-#include "ws_kernels.hpp"
+#include "ws_direct.hpp"
 
 #include <hip/hip_runtime.h>
 #include <algorithm>
@@ -93,6 +93,7 @@ struct ws_net {
   std::vector<Buf<float>> dpool, dmid_e, dcat, dmid_d, ddec;
   Buf<float> dbott, dy;
   float *scratch = nullptr;  // split-K partials
+  float *bias_rows = nullptr;  // per-row bias sums of an up-sampling weight gradient
   size_t scratch_floats = 0;
   double *loss_part = nullptr, *loss = nullptr;
   int n_loss_blocks = 0;
@@ -241,6 +242,52 @@ void split_plan(int P, int M, int N, int &splits, int &chunk) {
   splits = (P + chunk - 1) / chunk;
 }
 
+// Direct 3x3 kernels (ws_direct.hpp) serve a level whose image is a whole
+// number of 8 x 32 tiles and whose channel counts are multiples of 32 (the
+// staged operand may also be the 8-channel network input); other shapes, and
+// every layer under conv_algo = 1, use the implicit GEMM.
+bool direct_ok(const ws_net *n, const Img &g, int Kc, int Nc, bool c8_ok) {
+  return n->cfg.conv_algo == 0 && g.W % DT_W == 0 && g.H % DT_H == 0 && Nc % 32 == 0 &&
+         (Kc % 32 == 0 || (c8_ok && Kc == 8));
+}
+
+// Input channels per direct weight-gradient block (16 HW, 2 HW waves): 16
+// for the padded network input, 32 at 32 channels, else 64 (the FP32
+// output-gradient tile is staged once per block, so wider blocks read it
+// fewer times).
+int direct_whw(int Cin) { return Cin == 8 ? 1 : (Cin % 64 == 0 ? 4 : 2); }
+
+// Split plan of a direct weight gradient: about 3072 resident waves (12 per
+// CU) in all, each block summing a run of tiles.
+void direct_wplan(int ntiles, int Cin, int Cout, int &splits, int &tps) {
+  const int hw = direct_whw(Cin);
+  const int combos = std::max(1, Cin / (16 * hw)) * (Cout / 32);
+  const int want = std::max(1, 3072 / (2 * hw) / combos);
+  tps = std::max(1, (ntiles + want - 1) / want);
+  splits = (ntiles + tps - 1) / tps;
+}
+
+// A block computes 32 NW output channels with 4 NW waves (NW N groups share
+// each staged input tile, which is then read once per 32 NW channels, not
+// once per 32): NW = 2 where the output channels allow (four groups would
+// leave 128 registers per lane and spill), else 1.  Each block
+// runs enough tiles to leave about 512 blocks, so that one tile's loads
+// overlap the previous tile's MFMAs.
+template <bool BWD, bool C8, int NW>
+void launch_dconv_nw(ws_net *n, DConv p) {
+  const int nb = p.Nc / (32 * NW);
+  const int want = std::max(1, 512 / (nb * NW));
+  p.tpb = std::max(1, (p.T.n + want - 1) / want);
+  dim3 grid((unsigned)((p.T.n + p.tpb - 1) / p.tpb), (unsigned)nb);
+  hipLaunchKernelGGL((k_dconv<BWD, C8, NW>), grid, dim3(256 * NW), 0, n->stream, p);
+}
+
+template <bool BWD, bool C8>
+void launch_dconv(ws_net *n, const DConv &p) {
+  if (p.Nc % 64 == 0) launch_dconv_nw<BWD, C8, 2>(n, p);
+  else launch_dconv_nw<BWD, C8, 1>(n, p);
+}
+
 template <int KS, bool RELU, bool F32>
 int conv_fwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> out, View<float> outf) {
   ConvFwd<KS, RELU, F32> p;
@@ -258,6 +305,20 @@ int conv_fwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> 
 }
 
 int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> out) {
+  if (c.KS == 3 && c.relu && direct_ok(n, g, c.Cin, c.Cout, true)) {
+    DConv p{};
+    p.g = g;
+    p.T = DTiles::make(g.B, g.H, g.W);
+    p.x = in;
+    p.Kc = c.Cin;
+    p.Nc = c.Cout;
+    p.Wk = c.Wt;
+    p.bias = n->params + c.b_off;
+    p.y = out;
+    if (c.Cin == 8) launch_dconv<false, true>(n, p);
+    else launch_dconv<false, false>(n, p);
+    return WS_OK;
+  }
   return c.relu ? conv_fwd_t<3, true, false>(n, c, g, in, out, View<float>{nullptr, 0, 0})
                 : conv_fwd_t<3, false, false>(n, c, g, in, out, View<float>{nullptr, 0, 0});
 }
@@ -270,10 +331,15 @@ struct WShape {
 };
 WShape wshape(int Cout, int Kw1) { return Cout < 64 ? WShape{true, Kw1, Cout} : WShape{false, Cout, Kw1}; }
 
+// Sums split partials [splits][M][Kw+1] into dW [M][Kw] and the bias column
+// into db: directly when each row is one bias (Cb = M), else through bias_rows
+// folded as db[c] = sum over rows m = c (mod Cb) in ascending m.
 void launch_split_reduce(ws_net *n, int splits, int M, int Kw, float *dW, float *db, int Cb) {
-  const int64_t elems = (int64_t)M * Kw + Cb;
-  hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((elems + RED_E - 1) / RED_E)), dim3(RED_E * RED_G), 0,
-                     n->stream, n->scratch, splits, M, Kw, dW, db, Cb);
+  const int64_t E = (int64_t)M * (Kw + 1);
+  float *rows = Cb == M ? db : n->bias_rows;
+  hipLaunchKernelGGL(k_wreduce, dim3((unsigned)((E / 4 + 63) / 64)), dim3(64 * WR_G), 0, n->stream, n->scratch,
+                     splits, (int)E, Kw, dW, rows);
+  if (Cb != M) hipLaunchKernelGGL(k_bias_fold, dim3(1), dim3(256), 0, n->stream, (const float *)n->bias_rows, M, Cb, db);
 }
 
 template <int KS, bool RELU, bool TR>
@@ -298,14 +364,49 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
                View<float> din, int accumulate) {
   const int P = g.B * g.H * g.W;
   const int Kw = KS * KS * c.Cin;
-  const WShape ws = wshape(c.Cout, Kw + 1);
-  int splits, chunk;
-  split_plan(P, ws.M, ws.N, splits, chunk);
-  if ((size_t)splits * c.Cout * (Kw + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
-  if (ws.tr) conv_bwd_weight<KS, RELU, true>(n, c, g, in, act, dout, chunk, splits, ws);
-  else conv_bwd_weight<KS, RELU, false>(n, c, g, in, act, dout, chunk, splits, ws);
-  launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
-  if (din.p) {
+  if (KS == 3 && RELU && direct_ok(n, g, c.Cin, c.Cout, true)) {
+    DWGrad pw{};
+    pw.g = g;
+    pw.T = DTiles::make(g.B, g.H, g.W);
+    pw.dout = dout;
+    pw.act = act;
+    pw.in = in;
+    pw.Cin = c.Cin;
+    pw.Cout = c.Cout;
+    pw.partial = n->scratch;
+    int splits;
+    direct_wplan(pw.T.n, c.Cin, c.Cout, splits, pw.tps);
+    const int64_t E = (int64_t)c.Cout * (Kw + 1);
+    if ((size_t)splits * E > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+    const int hw = direct_whw(c.Cin);
+    const dim3 grid((unsigned)splits, (unsigned)(c.Cout / 32), (unsigned)std::max(1, c.Cin / (16 * hw)));
+    if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1>), grid, dim3(128), 0, n->stream, pw);
+    else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2>), grid, dim3(256), 0, n->stream, pw);
+    else hipLaunchKernelGGL((k_dwgrad<false, 4>), grid, dim3(512), 0, n->stream, pw);
+    launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
+  } else {
+    const WShape ws = wshape(c.Cout, Kw + 1);
+    int splits, chunk;
+    split_plan(P, ws.M, ws.N, splits, chunk);
+    if ((size_t)splits * c.Cout * (Kw + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+    if (ws.tr) conv_bwd_weight<KS, RELU, true>(n, c, g, in, act, dout, chunk, splits, ws);
+    else conv_bwd_weight<KS, RELU, false>(n, c, g, in, act, dout, chunk, splits, ws);
+    launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
+  }
+  if (!din.p) return WS_OK;
+  if (KS == 3 && RELU && direct_ok(n, g, c.Cout, c.Cin, false)) {
+    DConv pd{};
+    pd.g = g;
+    pd.T = DTiles::make(g.B, g.H, g.W);
+    pd.dx = dout;
+    pd.act = act;
+    pd.Kc = c.Cout;
+    pd.Nc = c.Cin;
+    pd.Wk = c.WtT;
+    pd.dy = din;
+    pd.accumulate = accumulate;
+    launch_dconv<true, false>(n, pd);
+  } else {
     ConvBwdData<KS, RELU> pd;
     pd.g = g;
     pd.dout = dout;
@@ -462,6 +563,7 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   if (c->base < 8 || c->base % 8) return fail(WS_EINVAL, "base channels must be a multiple of 8");
   if (c->cin < 1 || c->cin > 8 || c->cout < 1 || c->cout > 8) return fail(WS_EINVAL, "cin, cout must be 1..8");
   if (c->max_batch < 1) return fail(WS_EINVAL, "max_batch must be >= 1");
+  if (c->conv_algo < 0 || c->conv_algo > 1) return fail(WS_EINVAL, "conv_algo must be 0 or 1");
   const int div = 1 << (c->levels - 1);
   if (c->H % div || c->W % div) return fail(WS_EINVAL, "H and W must be divisible by 2^(levels-1)");
   // the up-sampling GEMM keeps one output parity per 64-row tile
@@ -553,6 +655,12 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
     auto conv = [&](int lv, const Conv &cv) {
       const WShape w = wshape(cv.Cout, cv.KS * cv.KS * cv.Cin + 1);
       need(lv, w.M, w.N);
+      const Img g = Img::make(B, imgH(n, lv), imgW(n, lv));
+      if (cv.KS == 3 && cv.relu && direct_ok(n, g, cv.Cin, cv.Cout, true)) {
+        int splits, tps;
+        direct_wplan(DTiles::make(B, g.H, g.W).n, cv.Cin, cv.Cout, splits, tps);
+        worst = std::max(worst, (size_t)splits * cv.Cout * (cv.KS * cv.KS * cv.Cin + 1));
+      }
     };
     for (int l = 0; l < L; ++l) {
       conv(l, n->e1[l]);
@@ -567,6 +675,7 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   }
   n->scratch_floats = worst;
   if (!rc) rc = dalloc(n, &n->scratch, worst);
+  if (!rc) rc = dalloc(n, &n->bias_rows, (size_t)4 * chans(n, L - 1));
   n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W * 8);
   if (!rc) rc = dalloc(n, &n->loss_part, n->n_loss_blocks);
   if (!rc) rc = dalloc(n, &n->loss, 1);
@@ -643,7 +752,7 @@ int ws_backward(ws_net *n, const float *x, const float *target, int32_t batch, d
   const int nb = (int)blocks((int64_t)P * 8);
   hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, n->stream, n->y.p, 8, target, P, n->cfg.cout, n->dy.p,
                      n->loss_part);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, n->stream, n->loss_part, nb,
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, n->stream, n->loss_part, nb,
                      1.0 / ((double)P * n->cfg.cout), n->loss);
   rc = backward(n, batch);
   if (rc) return rc;

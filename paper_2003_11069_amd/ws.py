@@ -26,7 +26,7 @@ class WSError(RuntimeError):
 
 class ws_config(C.Structure):
     _fields_ = [("levels", C.c_int32), ("base", C.c_int32), ("cin", C.c_int32), ("cout", C.c_int32),
-                ("H", C.c_int32), ("W", C.c_int32), ("max_batch", C.c_int32)]
+                ("H", C.c_int32), ("W", C.c_int32), ("max_batch", C.c_int32), ("conv_algo", C.c_int32)]
 
 
 _declared = None
@@ -131,9 +131,11 @@ class UNetConfig:
     H: int = 128
     W: int = 256
     max_batch: int = 8
+    conv_algo: int = 0  # 0: direct 3x3 kernels where the shape allows; 1: implicit GEMM only
 
     def to_c(self) -> ws_config:
-        return ws_config(self.levels, self.base, self.cin, self.cout, self.H, self.W, self.max_batch)
+        return ws_config(self.levels, self.base, self.cin, self.cout, self.H, self.W, self.max_batch,
+                         self.conv_algo)
 
 
 class UNet:

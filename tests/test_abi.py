@@ -102,7 +102,7 @@ def test_missing_library_fails_loudly(tmp_path):
 
 
 WS_BAD = [dict(levels=1), dict(levels=7), dict(base=12), dict(base=0), dict(cin=0), dict(cin=9),
-          dict(cout=9), dict(max_batch=0), dict(H=100), dict(H=8, W=8)]
+          dict(cout=9), dict(max_batch=0), dict(H=100), dict(H=8, W=8), dict(conv_algo=2), dict(conv_algo=-1)]
 
 
 @pytest.mark.parametrize("bad", WS_BAD)

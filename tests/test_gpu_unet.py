@@ -77,6 +77,10 @@ CASES = [
     (2, 8, 16, 32, 3),
     (3, 24, 32, 32, 2),
     (2, 16, 16, 32, 3),
+    # channel counts of 32 and 64 on whole 8 x 32 tiles: the direct 3x3 kernels
+    # (level 2 of the second, 8 x 16, falls back to the implicit GEMM)
+    (2, 32, 16, 64, 2),
+    (3, 32, 32, 64, 2),
 ]
 
 
@@ -180,7 +184,8 @@ def test_training_reduces_loss():
     assert l1 < 0.5 * l0
 
 
-EXACT = [(2, 8, 16, 32, 2, 4), (3, 24, 32, 32, 2, 2), (4, 32, 128, 256, 1, 2)]
+EXACT = [(2, 8, 16, 32, 2, 4), (3, 24, 32, 32, 2, 2), (2, 32, 16, 64, 2, 4), (3, 32, 32, 64, 1, 2),
+         (4, 32, 128, 256, 1, 2)]
 
 
 @pytest.mark.parametrize("L,base,H,W,B,cout", EXACT)
@@ -219,3 +224,28 @@ def test_exact_arithmetic_bit_identical(L, base, H, W, B, cout):
     assert len(bad_y) == 0
     assert loss == lo
     assert len(bad_g) == 0
+
+
+def test_direct_and_gemm_paths_agree_and_repeat():
+    """conv_algo 0 (direct 3x3 kernels) and 1 (implicit GEMM only) compute the
+    same network and differ only in FP32 summation order, so they agree to
+    the accumulation-noise bound; the direct path repeats bit for bit, and a
+    smaller batch uses only its images."""
+    L, base, H, W, B = 2, 32, 16, 64, 3
+    p = synth.unet_params(L, base, seed=3)
+    x, t = synth.unet_batch(B, H, W, 3, 3, seed=16)
+    res = {}
+    for algo in (0, 1):
+        net = ws.UNet(ws.UNetConfig(levels=L, base=base, cin=3, cout=3, H=H, W=W, max_batch=B, conv_algo=algo))
+        net.set_params(p)
+        y = net.forward(x)
+        net.backward(x, t)
+        res[algo] = (y, net.grads(), net)
+    (y0, g0, net0), (y1, g1, _) = res[0], res[1]
+    ey = np.linalg.norm(y0 - y1) / np.linalg.norm(y1)
+    eg = np.linalg.norm(g0.astype(np.float64) - g1) / np.linalg.norm(g1)
+    say(f"  direct vs implicit GEMM: y rel L2 {ey:.2e}, grad rel L2 {eg:.2e}")
+    assert ey <= tol_out(L) and eg <= tol_grad(L)
+    net0.backward(x, t)
+    assert np.array_equal(net0.grads(), g0)
+    assert np.array_equal(net0.forward(x[:2]), y0[:2])
