@@ -79,7 +79,7 @@ struct DConv {
 // walks (tile, 32-channel slice) items; the global loads of item i + 1 are
 // issued before the MFMAs of item i and land in registers, all of an item's
 // loads together, so memory latency overlaps the MFMAs.
-template <bool BWD, bool C8, int NW>
+template <bool BWD, bool C8, int NW, bool SL1>
 __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
   constexpr int NT = 2, BN = 32 * NW, NTH = 256 * NW;
   constexpr int XP = C8 ? 8 : DP;  // the padded input has one 8-channel chunk per pixel
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
   const int rg = wave & 3, ng = wave >> 2;  // row pair, N group
   const int n0 = blockIdx.y * BN, nw0 = n0 + 32 * ng, H = P.g.H, W = P.g.W;
-  const int slices = C8 ? 1 : P.Kc / 32;
+  const int slices = (C8 || SL1) ? 1 : P.Kc / 32;  // SL1: one 32-channel slice (weights staged once)
   const int blk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int t0 = blk * P.tpb, t1 = min(P.T.n, t0 + P.tpb);
   const int items = (t1 - t0) * slices;
@@ -109,55 +109,16 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
   float bias[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) bias[j] = BWD ? 0.f : P.bias[nw0 + 16 * j + l16];
-  // per-thread staging geometry, fixed for every tile: halo row and column of
-  // each item and its element offset from the tile's first pixel
-  int srr[XIT], scc[XIT], soff[XIT], aoff[XIT];
+  // per-thread staging geometry, fixed for every tile: each item's pixel
+  // offset from the tile's first pixel (its halo row and column are
+  // recomputed where needed, which costs fewer registers)
+  int rel[XIT];
 #pragma unroll
   for (int it = 0; it < XIT; ++it) {
-    const int q = tid + NTH * it;
-    const int pix = q / CPP, ch = (q - pix * CPP) * 8;
-    srr[it] = q < XN ? pix / DW : -1000;  // -1000: past the tile, never staged
-    scc[it] = pix - (pix / DW) * DW;
-    const int rel = (srr[it] - 1) * W + scc[it] - 1;
-    soff[it] = rel * (BWD ? P.dx.cs : P.x.cs) + ch;
-    aoff[it] = BWD ? rel * P.act.cs + ch : 0;
+    const int pix = (tid + NTH * it) / CPP, rr = pix / DW;
+    rel[it] = (rr - 1) * W + (pix - rr * DW) - 1;
   }
-  auto gload = [&](int item) {
-    float4 xg[BWD ? XIT : 1][2];
-    const int t = t0 + item / slices, s = item % slices;
-    int b, y0, x0;
-    P.T.at(t, b, y0, x0);
-    const int64_t tb = (int64_t)(b * H + y0) * W + x0;  // the tile's first pixel
-    const bf16 *xb = P.x.p + tb * P.x.cs + P.x.coff + s * 32;
-    const float *db = P.dx.p + tb * P.dx.cs + P.dx.coff + s * 32;
-    const bf16 *ab = P.act.p + tb * P.act.cs + P.act.coff + s * 32;
-#pragma unroll
-    for (int it = 0; it < XIT; ++it) {
-      const int yy = y0 + srr[it] - 1, xx = x0 + scc[it] - 1;
-      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-      if (BWD) {
-        xg[it][0] = xg[it][1] = float4{0.f, 0.f, 0.f, 0.f};
-        xa[it] = zero8();
-        if (in) {
-          const float4 *d = reinterpret_cast<const float4 *>(db + soff[it]);
-          xg[it][0] = d[0];
-          xg[it][1] = d[1];
-          xa[it] = *reinterpret_cast<const bf16x8 *>(ab + aoff[it]);
-        }
-      } else {
-        xa[it] = in ? *reinterpret_cast<const bf16x8 *>(xb + soff[it]) : zero8();
-      }
-    }
-    if (BWD) {  // output gradient times the ReLU mask, rounded to BF16
-#pragma unroll
-      for (int it = 0; it < XIT; ++it) {
-        const float f[8] = {xg[it][0].x, xg[it][0].y, xg[it][0].z, xg[it][0].w,
-                            xg[it][1].x, xg[it][1].y, xg[it][1].z, xg[it][1].w};
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xa[it][j] = (bf16)((float)xa[it][j] > 0.f ? f[j] : 0.f);
-      }
-    }
-    if (slices == 1 && item > 0) return;  // one slice: the weights stay in LDS
+  auto wload = [&](int s) {
 #pragma unroll
     for (int it = 0; it < WIT; ++it) {
       const int q = tid + NTH * it;
@@ -173,16 +134,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       }
     }
   };
-  auto lstore = [&](int item) {
-#pragma unroll
-    for (int it = 0; it < XIT; ++it) {
-      const int q = tid + NTH * it;
-      if (q < XN) {
-        const int pix = q / CPP, ch = (q - pix * CPP) * 8;
-        *reinterpret_cast<bf16x8 *>(&Xs[pix * XP + ch]) = xa[it];
-      }
-    }
-    if (slices == 1 && item > 0) return;
+  auto wstore = [&]() {
 #pragma unroll
     for (int it = 0; it < WIT; ++it) {
       const int q = tid + NTH * it;
@@ -192,6 +144,60 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       }
     }
   };
+  auto gload = [&](int item) {
+    float4 xg[BWD ? XIT : 1][2];
+    const int t = t0 + item / slices, s = item % slices;
+    int b, y0, x0;
+    P.T.at(t, b, y0, x0);
+    const int64_t tb = (int64_t)(b * H + y0) * W + x0;  // the tile's first pixel
+    const bf16 *xb = P.x.p + tb * P.x.cs + P.x.coff + s * 32;
+    const float *db = P.dx.p + tb * P.dx.cs + P.dx.coff + s * 32;
+    const bf16 *ab = P.act.p + tb * P.act.cs + P.act.coff + s * 32;
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int q = tid + NTH * it;
+      const int pix = q / CPP, ch = (q - pix * CPP) * 8, rr = pix / DW;
+      const int yy = y0 + rr - 1, xx = x0 + pix - rr * DW - 1;
+      const bool in = q < XN && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      if (BWD) {
+        xg[it][0] = xg[it][1] = float4{0.f, 0.f, 0.f, 0.f};
+        xa[it] = zero8();
+        if (in) {
+          const float4 *d = reinterpret_cast<const float4 *>(db + rel[it] * P.dx.cs + ch);
+          xg[it][0] = d[0];
+          xg[it][1] = d[1];
+          xa[it] = *reinterpret_cast<const bf16x8 *>(ab + rel[it] * P.act.cs + ch);
+        }
+      } else {
+        xa[it] = in ? *reinterpret_cast<const bf16x8 *>(xb + rel[it] * P.x.cs + ch) : zero8();
+      }
+    }
+    if (BWD) {  // output gradient times the ReLU mask, rounded to BF16
+#pragma unroll
+      for (int it = 0; it < XIT; ++it) {
+        const float f[8] = {xg[it][0].x, xg[it][0].y, xg[it][0].z, xg[it][0].w,
+                            xg[it][1].x, xg[it][1].y, xg[it][1].z, xg[it][1].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xa[it][j] = (bf16)((float)xa[it][j] > 0.f ? f[j] : 0.f);
+      }
+    }
+    if (!SL1) wload(s);
+  };
+  auto lstore = [&](int item) {
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int q = tid + NTH * it;
+      if (q < XN) {
+        const int pix = q / CPP, ch = (q - pix * CPP) * 8;
+        *reinterpret_cast<bf16x8 *>(&Xs[pix * XP + ch]) = xa[it];
+      }
+    }
+    if (!SL1) wstore();
+  };
+  if (SL1 && items > 0) {  // the one slice's weights, staged once
+    wload(0);
+    wstore();
+  }
   if (items > 0) gload(0);
   for (int item = 0; item < items; ++item) {
     if (item) __syncthreads();  // the previous item's reads are done
