@@ -351,6 +351,8 @@ def bench_unet(a):
     x, t = synth.unet_batch(B, Hh, Ww, 3, 3, seed=2)
     dx, dt = ws.DeviceArray.from_host(x), ws.DeviceArray.from_host(t)
     fwd, bwd = net.flops(B)
+    from paper_2003_11069_amd.lb import copy_probe
+    cp = copy_probe(1 << 30, iters=3)  # the reference copy of a counter run
     for _ in range(a.warmup):
         net.train_step_ptr(dx.ptr(), dt.ptr(), B, 1e-4)
     ws.sync()
@@ -368,7 +370,8 @@ def bench_unet(a):
                       "batch": B, "params": net.n_params, "gflop_per_sample_fwd": round(fwd / B / 1e9, 3),
                       "conv_algo": ["direct 3x3 where the shape allows", "implicit GEMM"][a.conv_algo]},
            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                        "frac": round(tflops / 2500.0, 4), "traffic": None}}
+                        "frac": round(tflops / 2500.0, 4), "traffic": None},
+           "copy_probe": {"GBps": round(cp["GBps"], 1)}}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -60,6 +60,39 @@ def counter_per_dispatch(db: str, counter: str):
     return out
 
 
+def counters_table(dbs, pattern: str, copy_bytes=None):
+    """Rows (kernel, grid in workgroups, dispatches, {counter: mean per
+    dispatch}) of every kernel whose name contains ``pattern``, from any
+    number of --pmc runs; FETCH_SIZE / WRITE_SIZE become bytes when a copy
+    kernel of ``copy_bytes`` read + written per dispatch ran in the same run."""
+    rows, scale = {}, {}
+    for db in dbs:
+        c = sqlite3.connect(db)
+        q = ("select kernel_name, dispatch_id, counter_name, sum(value), grid_size_x / workgroup_size_x, "
+             "grid_size_y, grid_size_z from counters_collection group by dispatch_id, counter_name")
+        per = {}
+        for name, did, cn, v, gx, gy, gz in c.execute(q).fetchall():
+            per.setdefault((name, gx, gy, gz, cn), []).append(float(v))
+        c.close()
+        for (name, gx, gy, gz, cn), vals in per.items():
+            if "k_copy_probe" in name and copy_bytes and cn in ("FETCH_SIZE", "WRITE_SIZE") and len(vals) > 1:
+                scale[cn] = copy_bytes / (statistics.median(vals[1:]) * 1024.0)
+            if pattern not in name:
+                continue
+            rows.setdefault((name, gx, gy, gz), {})[cn] = vals
+    out = []
+    for (name, gx, gy, gz), d in rows.items():
+        m = {}
+        for cn, vals in d.items():
+            v = statistics.mean(vals)
+            if cn in scale:
+                v = v * 1024.0 * scale[cn]
+            m[cn] = v
+        n = max(len(v) for v in d.values())
+        out.append((name, (gx, gy, gz), n, m))
+    return out, scale
+
+
 def _match(d: dict, key: str):
     names = [n for n in d if key in n]
     if not names:
@@ -80,6 +113,8 @@ def main(argv=None):
     ap.add_argument("--command", required=True, help="the command that produced the runs")
     ap.add_argument("--workload", default="")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--table", nargs="*", default=None,
+                    help="--pmc runs: per-kernel counter table of the kernels matching --kernel")
     a = ap.parse_args(argv)
 
     stats = trace_stats(a.trace)
@@ -117,6 +152,18 @@ def main(argv=None):
         if a.alg_bytes:
             lines.append(f"algorithmic_bytes_per_launch: {a.alg_bytes:.0f} (measured / algorithmic = "
                          f"{hbm / a.alg_bytes:.3f})")
+    if a.table:
+        rows, scale = counters_table(a.table, a.kernel, a.copy_bytes)
+        cns = sorted({cn for _, _, _, m in rows for cn in m})
+        lines += ["", f"## counters per dispatch (--pmc runs; mean over dispatches of one grid)"]
+        if scale:
+            lines.append("FETCH_SIZE / WRITE_SIZE in bytes, scaled by the copy kernel: " +
+                         ", ".join(f"{k} x {v:.4f}" for k, v in sorted(scale.items())))
+        lines.append(f"{'kernel':<44} {'grid':>14} " + " ".join(f"{cn[:22]:>22}" for cn in cns))
+        for name, g, n, m in sorted(rows, key=lambda r: (r[0], r[1])):
+            short = name.replace("void ", "").split("(")[0][:44]
+            lines.append(f"{short:<44} {str(g):>14} " +
+                         " ".join(f"{m[cn]:>22.4g}" if cn in m else f"{'-':>22}" for cn in cns))
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
