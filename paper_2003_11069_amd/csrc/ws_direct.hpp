@@ -9,7 +9,7 @@
 //
 //   k_dconv   forward (BF16 input; bias, ReLU, BF16 output) and backward-data
 //             (output gradient times the ReLU mask, rounded to BF16 while
-//             staging; FP32 output, stored or added).  The staged operand has
+//             staging; FP32 output).  The staged operand has
 //             Kc channels (a multiple of 32, or the 8 of the padded network
 //             input), the output Nc (a multiple of 32).  Weights [Nc][9][Kc]:
 //             the forward W, or for backward-data its flipped transpose.
@@ -68,8 +68,11 @@ struct DConv {
   const bf16 *Wk;        // [Nc][9][Kc]
   const float *bias;     // forward
   View<bf16> y;          // forward output (Nc channels)
-  View<float> dy;        // backward-data output
-  int accumulate;        // backward-data: add to dy
+  View<float> dy;        // backward-data output (stored, not added)
+  bf16 *dpre;            // backward-data: when set, the BF16 operand (output
+                         // gradient x mask) of every tile's own pixels is
+                         // also written here, [pixel][Kc], for the weight
+                         // gradient (by the blocks of the first N group)
 };
 
 // Block: a run of tpb tiles x 32 NW output channels (blockIdx.y), 4 NW
@@ -180,6 +183,15 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) xa[it][j] = (bf16)((float)xa[it][j] > 0.f ? f[j] : 0.f);
       }
+      if (P.dpre && n0 == 0) {  // the tile's own pixels, for the weight gradient
+#pragma unroll
+        for (int it = 0; it < XIT; ++it) {
+          const int q = tid + NTH * it;
+          const int pix = q / CPP, ch = (q - pix * CPP) * 8, rr = pix / DW, cc = pix - rr * DW;
+          if (q < XN && rr >= 1 && rr <= DT_H && cc >= 1 && cc <= DT_W)
+            *reinterpret_cast<bf16x8 *>(P.dpre + (size_t)(tb + rel[it]) * P.Kc + s * 32 + ch) = xa[it];
+        }
+      }
     }
     if (!SL1) wload(s);
   };
@@ -232,21 +244,10 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       }
     }
     if (item % slices != slices - 1) continue;
-    // the tile's last slice: bias and ReLU (forward) and store (no loads
-    // here but the accumulating case's, which would wait for the prefetch)
+    // the tile's last slice: bias and ReLU (forward) and store (no global
+    // loads here: they would wait for the prefetch)
     int b, y0, x0;
     P.T.at(t0 + item / slices, b, y0, x0);
-    if (BWD && P.accumulate) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < NT; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const size_t p = (size_t)(b * H + y0 + 2 * rg + (i >> 1)) * W + x0 + 16 * (i & 1) + 4 * g + q;
-            acc[i][j][q] += P.dy.p[p * P.dy.cs + P.dy.coff + nw0 + 16 * j + l16];
-          }
-    }
     if (BWD || NW > 1) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -307,6 +308,7 @@ struct DWGrad {
   View<const bf16> in;     // the layer's input (Cin channels)
   int Cin, Cout;
   float *partial;          // [splits][Cout][9 Cin + 1]
+  const bf16 *dpre;        // DPRE: the BF16 operand (output gradient x mask), [pixel][Cout]
 };
 
 constexpr int WA_P = DT_H * DT_W + 8;  // co pitch (bf16) of the transposed output gradient: 528 B
@@ -318,7 +320,7 @@ constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
 // waves.  Wave w: output channels 16 (w & 1), input channels 16 (w >> 1), all
 // nine taps; K = the 32 pixels of one tile row.  The output-gradient tile
 // (the FP32 operand) is staged once for all 16 HW input channels.
-template <bool C8, int HW>
+template <bool C8, int HW, bool DPRE>
 __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   constexpr int CI = 16 * HW, NTH = 128 * HW;
   __shared__ __attribute__((aligned(16))) bf16 As[32 * WA_P];  // dPre^T [co][r][c]
@@ -339,8 +341,8 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   // per item: FP32 values and the mask), input (two pixels x 8 channels)
   constexpr int AN = DT_H * DT_W / 2 * 4, AIT = AN / NTH;
   constexpr int NCH = CI / 8, BN_ = DH * (DW / 2) * NCH, BIT = (BN_ + NTH - 1) / NTH;
-  float4 ga[AIT][4];
-  bf16x8 ma[AIT][2], ib[BIT][2];
+  float4 ga[DPRE ? 1 : AIT][4];
+  bf16x8 ma[AIT][2], ib[BIT][2];  // DPRE: ma holds the BF16 operand itself
   auto gload = [&](int t) {
     int b, y0, x0;
     P.T.at(t, b, y0, x0);
@@ -352,10 +354,14 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const size_t o = (size_t)(p + e);
-        const float4 *d = reinterpret_cast<const float4 *>(P.dout.p + o * P.dout.cs + P.dout.coff + co0 + 8 * cq);
-        ga[it][2 * e] = d[0];
-        ga[it][2 * e + 1] = d[1];
-        ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.act.p + o * P.act.cs + P.act.coff + co0 + 8 * cq);
+        if constexpr (DPRE) {
+          ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.dpre + o * P.Cout + co0 + 8 * cq);
+        } else {
+          const float4 *d = reinterpret_cast<const float4 *>(P.dout.p + o * P.dout.cs + P.dout.coff + co0 + 8 * cq);
+          ga[it][2 * e] = d[0];
+          ga[it][2 * e + 1] = d[1];
+          ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.act.p + o * P.act.cs + P.act.coff + co0 + 8 * cq);
+        }
       }
     }
 #pragma unroll
@@ -379,10 +385,15 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
       bf16 v[2][8];
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        const float f[8] = {ga[it][2 * e].x, ga[it][2 * e].y, ga[it][2 * e].z, ga[it][2 * e].w,
-                            ga[it][2 * e + 1].x, ga[it][2 * e + 1].y, ga[it][2 * e + 1].z, ga[it][2 * e + 1].w};
+        if constexpr (DPRE) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[e][j] = (bf16)((float)ma[it][e][j] > 0.f ? f[j] : 0.f);
+          for (int j = 0; j < 8; ++j) v[e][j] = ma[it][e][j];
+        } else {
+          const float f[8] = {ga[it][2 * e].x, ga[it][2 * e].y, ga[it][2 * e].z, ga[it][2 * e].w,
+                              ga[it][2 * e + 1].x, ga[it][2 * e + 1].y, ga[it][2 * e + 1].z, ga[it][2 * e + 1].w};
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[e][j] = (bf16)((float)ma[it][e][j] > 0.f ? f[j] : 0.f);
+        }
       }
 #pragma unroll
       for (int j = 0; j < 8; ++j)

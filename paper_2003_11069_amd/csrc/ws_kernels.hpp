@@ -273,7 +273,7 @@ __device__ __forceinline__ bf16x8 grad8(const View<const float> &d, const View<c
 
 // Backward-data of ConvFwd: dIn[p, ci] = sum_{ky,kx,co} WtT[ci][(ky*KS+kx)*Cout + co]
 //   dPre[p + (ky-r, kx-r), co],  WtT = weights flipped in (ky,kx) and transposed.
-// M = pixels, N = Cin, K = KS*KS*Cout (Cout multiple of 8).  Writes or adds FP32.
+// M = pixels, N = Cin, K = KS*KS*Cout (Cout multiple of 8).  Writes FP32.
 template <int KS, bool RELU>
 struct ConvBwdData {
   static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
@@ -284,7 +284,6 @@ struct ConvBwdData {
   Div dCout;
   const bf16 *WtT;  // [Cin][K]
   View<float> din;
-  int accumulate;
   __device__ __forceinline__ int K() const { return KS * KS * Cout; }
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = K(); }
   __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
@@ -303,7 +302,7 @@ struct ConvBwdData {
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     if (m >= g.P() || n >= Cin) return;
     float *d = din.p + (size_t)m * din.cs + din.coff + n;
-    *d = accumulate ? *d + v : v;
+    *d = v;
   }
 };
 

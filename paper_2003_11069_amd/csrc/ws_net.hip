@@ -94,6 +94,7 @@ struct ws_net {
   Buf<float> dbott, dy;
   float *scratch = nullptr;  // split-K partials
   float *bias_rows = nullptr;  // per-row bias sums of an up-sampling weight gradient
+  bf16 *dpre = nullptr;        // BF16 backward operand of a layer, data gradient -> weight gradient
   size_t scratch_floats = 0;
   double *loss_part = nullptr, *loss = nullptr;
   int n_loss_blocks = 0;
@@ -365,10 +366,41 @@ void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<
 // weight and bias gradients of a conv layer, then (if din.p) its data gradient
 template <int KS, bool RELU>
 int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act, View<const float> dout,
-               View<float> din, int accumulate) {
+               View<float> din) {
   const int P = g.B * g.H * g.W;
   const int Kw = KS * KS * c.Cin;
-  if (KS == 3 && RELU && direct_ok(n, g, c.Cin, c.Cout, true)) {
+  const bool wdirect = KS == 3 && RELU && direct_ok(n, g, c.Cin, c.Cout, true);
+  const bool ddirect = din.p && KS == 3 && RELU && direct_ok(n, g, c.Cout, c.Cin, false);
+  // with both gradients direct, the data gradient (first) leaves the BF16
+  // operand (output gradient x mask) of every pixel for the weight gradient
+  bf16 *dpre = (wdirect && ddirect) ? n->dpre : nullptr;
+  if (din.p) {
+    if (ddirect) {
+      DConv pd{};
+      pd.g = g;
+      pd.T = DTiles::make(g.B, g.H, g.W);
+      pd.dx = dout;
+      pd.act = act;
+      pd.Kc = c.Cout;
+      pd.Nc = c.Cin;
+      pd.Wk = c.WtT;
+      pd.dy = din;
+      pd.dpre = dpre;
+      launch_dconv<true, false>(n, pd);
+    } else {
+      ConvBwdData<KS, RELU> pd;
+      pd.g = g;
+      pd.dout = dout;
+      pd.act = act;
+      pd.Cin = c.Cin;
+      pd.Cout = c.Cout;
+      pd.WtT = c.WtT;
+      pd.din = din;
+      pd.dCout = Div::make(c.Cout);
+      gemm(n, pd, P, c.Cin, 1, pick_tile(P, c.Cin, 0));
+    }
+  }
+  if (wdirect) {
     DWGrad pw{};
     pw.g = g;
     pw.T = DTiles::make(g.B, g.H, g.W);
@@ -378,15 +410,18 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     pw.Cin = c.Cin;
     pw.Cout = c.Cout;
     pw.partial = n->scratch;
+    pw.dpre = dpre;
     int splits;
     direct_wplan(pw.T.n, c.Cin, c.Cout, splits, pw.tps);
     const int64_t E = (int64_t)c.Cout * (Kw + 1);
     if ((size_t)splits * E > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
     const int hw = direct_whw(c.Cin);
     const dim3 grid((unsigned)splits, (unsigned)(c.Cout / 32), (unsigned)std::max(1, c.Cin / (16 * hw)));
-    if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1>), grid, dim3(128), 0, n->stream, pw);
-    else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2>), grid, dim3(256), 0, n->stream, pw);
-    else hipLaunchKernelGGL((k_dwgrad<false, 4>), grid, dim3(512), 0, n->stream, pw);
+    if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1, false>), grid, dim3(128), 0, n->stream, pw);
+    else if (hw == 2 && dpre) hipLaunchKernelGGL((k_dwgrad<false, 2, true>), grid, dim3(256), 0, n->stream, pw);
+    else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2, false>), grid, dim3(256), 0, n->stream, pw);
+    else if (dpre) hipLaunchKernelGGL((k_dwgrad<false, 4, true>), grid, dim3(512), 0, n->stream, pw);
+    else hipLaunchKernelGGL((k_dwgrad<false, 4, false>), grid, dim3(512), 0, n->stream, pw);
     launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   } else {
     const WShape ws = wshape(c.Cout, Kw + 1);
@@ -396,32 +431,6 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     if (ws.tr) conv_bwd_weight<KS, RELU, true>(n, c, g, in, act, dout, chunk, splits, ws);
     else conv_bwd_weight<KS, RELU, false>(n, c, g, in, act, dout, chunk, splits, ws);
     launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
-  }
-  if (!din.p) return WS_OK;
-  if (KS == 3 && RELU && direct_ok(n, g, c.Cout, c.Cin, false)) {
-    DConv pd{};
-    pd.g = g;
-    pd.T = DTiles::make(g.B, g.H, g.W);
-    pd.dx = dout;
-    pd.act = act;
-    pd.Kc = c.Cout;
-    pd.Nc = c.Cin;
-    pd.Wk = c.WtT;
-    pd.dy = din;
-    pd.accumulate = accumulate;
-    launch_dconv<true, false>(n, pd);
-  } else {
-    ConvBwdData<KS, RELU> pd;
-    pd.g = g;
-    pd.dout = dout;
-    pd.act = act;
-    pd.Cin = c.Cin;
-    pd.Cout = c.Cout;
-    pd.WtT = c.WtT;
-    pd.din = din;
-    pd.accumulate = accumulate;
-    pd.dCout = Div::make(c.Cout);
-    gemm(n, pd, P, c.Cin, 1, pick_tile(P, c.Cin, 0));
   }
   return WS_OK;
 }
@@ -515,13 +524,13 @@ int backward(ws_net *n, int B) {
   const int L = n->L;
   Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
   int rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), View<const bf16>{nullptr, 0, 0}, cv(n->dy),
-                                mv(n->ddec[0]), 0);
+                                mv(n->ddec[0]));
   if (rc) return rc;
   for (int l = 0; l <= L - 2; ++l) {
     Img gl = Img::make(B, imgH(n, l), imgW(n, l)), gu = Img::make(B, imgH(n, l + 1), imgW(n, l + 1));
-    rc = conv_bwd_t<3, true>(n, n->d2[l], gl, cv(n->mid_d[l]), cv(n->dec[l]), cv(n->ddec[l]), mv(n->dmid_d[l]), 0);
+    rc = conv_bwd_t<3, true>(n, n->d2[l], gl, cv(n->mid_d[l]), cv(n->dec[l]), cv(n->ddec[l]), mv(n->dmid_d[l]));
     if (rc) return rc;
-    rc = conv_bwd_t<3, true>(n, n->d1[l], gl, cv(n->cat[l]), cv(n->mid_d[l]), cv(n->dmid_d[l]), mv(n->dcat[l]), 0);
+    rc = conv_bwd_t<3, true>(n, n->d1[l], gl, cv(n->cat[l]), cv(n->mid_d[l]), cv(n->dmid_d[l]), mv(n->dcat[l]));
     if (rc) return rc;
     View<const bf16> uin = l == L - 2 ? cv(n->bott) : cv(n->dec[l + 1]);
     View<float> dup = l == L - 2 ? mv(n->dbott) : mv(n->ddec[l + 1]);
@@ -533,11 +542,11 @@ int backward(ws_net *n, int B) {
     const int C = chans(n, l);
     View<const bf16> eout = l < L - 1 ? cv(n->cat[l], C) : cv(n->bott);
     View<const float> deout = l < L - 1 ? cv(n->dcat[l], C) : cv(n->dbott);
-    rc = conv_bwd_t<3, true>(n, n->e2[l], g, cv(n->mid_e[l]), eout, deout, mv(n->dmid_e[l]), 0);
+    rc = conv_bwd_t<3, true>(n, n->e2[l], g, cv(n->mid_e[l]), eout, deout, mv(n->dmid_e[l]));
     if (rc) return rc;
     View<const bf16> in = l == 0 ? cv(n->xin) : cv(n->pool[l]);
     View<float> din = l == 0 ? View<float>{nullptr, 0, 0} : mv(n->dpool[l]);
-    rc = conv_bwd_t<3, true>(n, n->e1[l], g, in, cv(n->mid_e[l]), cv(n->dmid_e[l]), din, 0);
+    rc = conv_bwd_t<3, true>(n, n->e1[l], g, in, cv(n->mid_e[l]), cv(n->dmid_e[l]), din);
     if (rc) return rc;
     if (l > 0) {  // route the pooled gradient into the level l-1 encoder output
       Img gp = Img::make(B, imgH(n, l - 1), imgW(n, l - 1));
@@ -680,6 +689,8 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   n->scratch_floats = worst;
   if (!rc) rc = dalloc(n, &n->scratch, worst);
   if (!rc) rc = dalloc(n, &n->bias_rows, (size_t)4 * chans(n, L - 1));
+  // the largest direct layer's output gradient: C_l channels on H W / 4^l pixels
+  if (!rc) rc = dalloc(n, &n->dpre, c->conv_algo == 0 ? (size_t)c->max_batch * c->H * c->W * c->base : 1);
   n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W * 8);
   if (!rc) rc = dalloc(n, &n->loss_part, n->n_loss_blocks);
   if (!rc) rc = dalloc(n, &n->loss, 1);
