@@ -511,6 +511,73 @@ static __global__ __launch_bounds__(64 * WR_G) void k_wreduce(const float *parti
   }
 }
 
+// ---------------------------------------------------------------------------
+// 2x2 stride-2 transposed convolution (up-sampling), forward, for an input
+// image whose width is a multiple of 32, without the implicit GEMM's
+// scattered 2-byte stores.  A block owns a 32-pixel segment of one input
+// row; wave d (parity dy = d >> 1, dx = d & 1) computes
+//   out[(2y+dy, 2x+dx), co] = b[co] + sum_ci W[d][co][ci] in[(y,x), ci]
+// for the segment's 32 pixels and all Cout channels and writes them as
+// 16-byte rows through LDS.  (A direct data gradient, with each wave loading
+// its FP32 operand itself, measured slower than the implicit GEMM, which
+// stages it once per block: 18.5 -> 41 us at level 0; it is not used.)
+struct DUp {
+  Img g;                  // input image
+  int segs;               // 32-pixel segments per input row
+  int Cin, Cout;
+  View<const bf16> in;    // input (Cin channels)
+  const bf16 *Wt;         // [4][Cout][Cin]
+  const float *bias;
+  View<bf16> out;         // output image, 2H x 2W (Cout channels)
+};
+
+template <int NT>  // NT = Cout / 16
+__global__ __launch_bounds__(256) void k_upfwd(DUp P) {
+  constexpr int OPU = 16 * NT + 8;  // LDS pixel pitch of the staged output (bf16)
+  __shared__ __attribute__((aligned(16))) bf16 Os[4][32 * OPU];
+  const int lane = threadIdx.x & 63, d = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int H = P.g.H, W = P.g.W;
+  const int seg = blockIdx.x, x0 = (seg % P.segs) * 32, row = seg / P.segs;  // row = b H + y
+  const int y = row % H, b = row / H;
+  f4 acc[2][NT];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const bf16 *ip = P.in.p + ((size_t)row * W + x0) * P.in.cs + P.in.coff;
+  for (int k0 = 0; k0 < P.Cin; k0 += 32) {
+    bf16x8 a[2], bw[NT];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const bf16x8 *>(ip + (size_t)(16 * i + l16) * P.in.cs + k0 + 8 * g);
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      bw[j] = *reinterpret_cast<const bf16x8 *>(P.Wt + ((size_t)d * P.Cout + 16 * j + l16) * P.Cin + k0 + 8 * g);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[j], acc[i][j], 0, 0, 0);
+  }
+  bf16 *O = Os[d];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const float bj = P.bias[16 * j + l16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) O[(16 * i + 4 * g + q) * OPU + 16 * j + l16] = (bf16)(acc[i][j][q] + bj);
+  }
+  __syncthreads();
+  const int Y = 2 * y + (d >> 1), dx = d & 1;
+  constexpr int CH = 2 * NT;  // 16-byte chunks per output pixel
+  for (int e = lane; e < 32 * CH; e += 64) {
+    const int px = e / CH, c8 = (e - px * CH) * 8;
+    const size_t q = ((size_t)b * 2 * H + Y) * 2 * W + 2 * (x0 + px) + dx;
+    *reinterpret_cast<bf16x8 *>(P.out.p + q * P.out.cs + P.out.coff + c8) =
+        *reinterpret_cast<const bf16x8 *>(&O[px * OPU + c8]);
+  }
+}
+
 // db[c] = sum over m = c, c + Cb, ... < M of rows[m], in ascending m.
 static __global__ __launch_bounds__(256) void k_bias_fold(const float *rows, int M, int Cb, float *db) {
   for (int c = threadIdx.x; c < Cb; c += 256) {

@@ -437,7 +437,31 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
   return WS_OK;
 }
 
+// The direct up-sampling forward serves input rows that are whole 32-pixel
+// segments with Cout of 32, 64 or 128; the implicit GEMM covers the rest,
+// both up-sampling gradients, and conv_algo = 1.
+bool up_direct_fwd(const ws_net *n, const Img &gin, const Up &u) {
+  return n->cfg.conv_algo == 0 && gin.W % 32 == 0 && (u.Cout == 32 || u.Cout == 64 || u.Cout == 128) &&
+         u.Cin % 32 == 0;
+}
+
 int up_fwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<bf16> out) {
+  if (up_direct_fwd(n, gin, u)) {
+    DUp p{};
+    p.g = gin;
+    p.segs = gin.W / 32;
+    p.Cin = u.Cin;
+    p.Cout = u.Cout;
+    p.in = in;
+    p.Wt = u.Wt;
+    p.bias = n->params + u.b_off;
+    p.out = out;
+    const dim3 grid((unsigned)(gin.B * gin.H * p.segs));
+    if (u.Cout == 32) hipLaunchKernelGGL(k_upfwd<2>, grid, dim3(256), 0, n->stream, p);
+    else if (u.Cout == 64) hipLaunchKernelGGL(k_upfwd<4>, grid, dim3(256), 0, n->stream, p);
+    else hipLaunchKernelGGL(k_upfwd<8>, grid, dim3(256), 0, n->stream, p);
+    return WS_OK;
+  }
   UpFwd p;
   p.g = gin;
   p.in = in;
