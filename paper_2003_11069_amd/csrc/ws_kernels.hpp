@@ -471,21 +471,48 @@ struct UpBwdWeight {
 // ---------------------------------------------------------------------------
 // 2x2 max pooling (stride 2): forward on BF16, backward routes the gradient to
 // the first maximum in the order (0,0), (0,1), (1,0), (1,1) and adds it to the
-// input gradient.
-static __global__ __launch_bounds__(256) void k_pool_fwd(Img g, View<const bf16> in, int C, View<bf16> out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // output element
+// input gradient.  The forward handles one pooled pixel and 8 channels (C is
+// a multiple of 8) per thread, with 16-byte vectors.
+__device__ __forceinline__ void pool_split(const Img &g, int i, int C8, int &c, int &t, int &b, int &y, int &x) {
   const int Ho = g.H / 2, Wo = g.W / 2;
-  if (i >= g.B * Ho * Wo * C) return;
-  const int c = i % C, t = i / C, x = t % Wo, t2 = t / Wo, y = t2 % Ho, b = t2 / Ho;
-  float best = -INFINITY;
-  for (int d = 0; d < 4; ++d) {
-    const size_t q = ((size_t)b * g.H + 2 * y + (d >> 1)) * g.W + 2 * x + (d & 1);
-    const float v = (float)in.p[q * in.cs + in.coff + c];
-    if (v > best) best = v;
-  }
-  out.p[(size_t)t * out.cs + out.coff + c] = (bf16)best;
+  c = (i % C8) * 8;
+  t = i / C8;  // pooled pixel
+  x = t % Wo;
+  const int t2 = t / Wo;
+  y = t2 % Ho;
+  b = t2 / Ho;
+}
+__device__ __forceinline__ size_t pool_src(const Img &g, int b, int y, int x, int d) {
+  return ((size_t)b * g.H + 2 * y + (d >> 1)) * g.W + 2 * x + (d & 1);
 }
 
+static __global__ __launch_bounds__(256) void k_pool_fwd(Img g, View<const bf16> in, int C, View<bf16> out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // (pooled pixel, 8-channel chunk)
+  const int C8 = C / 8;
+  if (i >= g.B * (g.H / 2) * (g.W / 2) * C8) return;
+  int c, t, b, y, x;
+  pool_split(g, i, C8, c, t, b, y, x);
+  bf16x8 v[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+    v[d] = *reinterpret_cast<const bf16x8 *>(in.p + pool_src(g, b, y, x, d) * in.cs + in.coff + c);
+  bf16x8 r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    float best = -INFINITY;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const float f = (float)v[d][j];
+      if (f > best) best = f;
+    }
+    r[j] = (bf16)best;
+  }
+  *reinterpret_cast<bf16x8 *>(out.p + (size_t)t * out.cs + out.coff + c) = r;
+}
+
+// Backward: a thread per pooled element (consecutive threads take consecutive
+// channels, so the read-modify-write of the maximum's element is coalesced;
+// 8-channel vectors measured slower here).
 static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16> in, int C, View<const float> dout,
                                                   View<float> din) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -503,30 +530,42 @@ static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16>
   din.p[q * din.cs + din.coff + c] += dout.p[(size_t)t * dout.cs + dout.coff + c];
 }
 
-// Network input: FP32 NHWC [P][cin] -> BF16 [P][8] (channels padded with zeros).
+// Network input: FP32 NHWC [P][cin] -> BF16 [P][8] (channels padded with
+// zeros), a pixel per thread.
 static __global__ __launch_bounds__(256) void k_pack_input(const float *x, int P, int cin, bf16 *out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P * 8) return;
-  const int p = i / 8, c = i % 8;
-  out[i] = (bf16)(c < cin ? x[(size_t)p * cin + c] : 0.f);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  bf16x8 v;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = (bf16)(c < cin ? x[(size_t)p * cin + c] : 0.f);
+  *reinterpret_cast<bf16x8 *>(out + (size_t)p * 8) = v;
 }
 
-// MSE over the first `cout` channels of the head output (stride cs): per-block
-// partial sums (fixed order) and dY = 2 (y - t) / (P cout), zero padding.
-static __global__ __launch_bounds__(256) void k_mse(const float *y, int cs, const float *t, int P, int cout,
-                                             float *dy, double *partial) {
+// MSE over the first `cout` channels of the head output (8 channels per
+// pixel), a pixel per thread: per-block partial sums (the pixel's channels in
+// order, then a fixed tree) and dY = 2 (y - t) / (P cout), zero padding.
+static __global__ __launch_bounds__(256) void k_mse(const float *y, const float *t, int P, int cout, float *dy,
+                                             double *partial) {
   __shared__ double sh[256];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   double e = 0.0;
-  if (i < P * cs) {
-    const int p = i / cs, c = i % cs;
-    float g = 0.f;
-    if (c < cout) {
-      const float d = y[i] - t[(size_t)p * cout + c];
-      e = (double)d * d;
-      g = 2.f * d / (float)((double)P * cout);
+  if (p < P) {
+    const float4 *ys = reinterpret_cast<const float4 *>(y + (size_t)p * 8);
+    const float4 y0 = ys[0], y1 = ys[1];
+    const float yv[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+    float gv[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      gv[c] = 0.f;
+      if (c < cout) {
+        const float d = yv[c] - t[(size_t)p * cout + c];
+        e += (double)d * d;
+        gv[c] = 2.f * d / (float)((double)P * cout);
+      }
     }
-    dy[i] = g;
+    float4 *ds = reinterpret_cast<float4 *>(dy + (size_t)p * 8);
+    ds[0] = float4{gv[0], gv[1], gv[2], gv[3]};
+    ds[1] = float4{gv[4], gv[5], gv[6], gv[7]};
   }
   sh[threadIdx.x] = e;
   __syncthreads();

@@ -512,8 +512,7 @@ View<T> mv(Buf<T> &b, int coff = 0) { return View<T>{b.p, b.cs, coff}; }
 int forward(ws_net *n, const float *x, int B) {
   const int L = n->L;
   const int P0 = B * n->cfg.H * n->cfg.W;
-  hipLaunchKernelGGL(k_pack_input, dim3(blocks((int64_t)P0 * 8)), dim3(256), 0, n->stream, x, P0, n->cfg.cin,
-                     n->xin.p);
+  hipLaunchKernelGGL(k_pack_input, dim3(blocks(P0)), dim3(256), 0, n->stream, x, P0, n->cfg.cin, n->xin.p);
   for (int l = 0; l < L; ++l) {
     Img g = Img::make(B, imgH(n, l), imgW(n, l));
     const int C = chans(n, l);
@@ -524,7 +523,7 @@ int forward(ws_net *n, const float *x, int B) {
     rc = conv_fwd(n, n->e2[l], g, cv(n->mid_e[l]), eout);
     if (rc) return rc;
     if (l < L - 1) {
-      const int64_t cnt = (int64_t)B * (g.H / 2) * (g.W / 2) * C;
+      const int64_t cnt = (int64_t)B * (g.H / 2) * (g.W / 2) * (C / 8);  // 8 channels per thread
       hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, g,
                          View<const bf16>{eout.p, eout.cs, eout.coff}, C, mv(n->pool[l + 1]));
     }
@@ -717,7 +716,7 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   if (!rc) rc = dalloc(n, &n->bias_rows, (size_t)4 * chans(n, L - 1));
   // the largest direct layer's output gradient: C_l channels on H W / 4^l pixels
   if (!rc) rc = dalloc(n, &n->dpre, c->conv_algo == 0 ? (size_t)c->max_batch * c->H * c->W * c->base : 1);
-  n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W * 8);
+  n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W);  // k_mse: a pixel per thread
   if (!rc) rc = dalloc(n, &n->loss_part, n->n_loss_blocks);
   if (!rc) rc = dalloc(n, &n->loss, 1);
   if (!rc) {
@@ -790,8 +789,8 @@ int ws_backward(ws_net *n, const float *x, const float *target, int32_t batch, d
   rc = forward(n, x, batch);
   if (rc) return rc;
   const int P = batch * n->cfg.H * n->cfg.W;
-  const int nb = (int)blocks((int64_t)P * 8);
-  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, n->stream, n->y.p, 8, target, P, n->cfg.cout, n->dy.p,
+  const int nb = (int)blocks(P);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, n->stream, n->y.p, target, P, n->cfg.cout, n->dy.p,
                      n->loss_part);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, n->stream, n->loss_part, nb,
                      1.0 / ((double)P * n->cfg.cout), n->loss);
