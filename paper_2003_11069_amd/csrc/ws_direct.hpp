@@ -1,24 +1,31 @@
-// ws_direct.hpp -- direct 3x3 convolutions (stride 1, zero padding 1) of the
-// warm-start U-Net on v_mfma_f32_16x16x32_bf16, for images whose width is a
-// multiple of 32 and height a multiple of 8.
+// ws_direct.hpp -- direct kernels of the warm-start U-Net on
+// v_mfma_f32_16x16x32_bf16: 3x3 convolutions (stride 1, zero padding 1) of
+// images whose width is a multiple of 32 and height a multiple of 8, and the
+// up-sampling forward of rows of whole 32-pixel segments.
 //
-// A block owns one 8 x 32 pixel tile of one image.  It stages the tile and
-// its one-pixel halo in LDS once per 32-channel slice and reads all nine taps
-// from there (the implicit GEMM of ws_kernels.hpp gathers every tap from
-// global memory, and converts a backward operand once per tap).
+// A convolution block works through a run of 8 x 32 pixel tiles of one
+// image.  It stages each tile and its one-pixel halo in LDS once per
+// 32-channel slice and reads all nine taps from there (the implicit GEMM of
+// ws_kernels.hpp gathers every tap from global memory, and converts a
+// backward operand once per tap).
 //
-//   k_dconv   forward (BF16 input; bias, ReLU, BF16 output) and backward-data
-//             (output gradient times the ReLU mask, rounded to BF16 while
-//             staging; FP32 output).  The staged operand has
-//             Kc channels (a multiple of 32, or the 8 of the padded network
-//             input), the output Nc (a multiple of 32).  Weights [Nc][9][Kc]:
-//             the forward W, or for backward-data its flipped transpose.
-//   k_dwgrad  weight and bias gradient.  Both operands are staged transposed
-//             (pixels contiguous, the reduction dimension of the MFMA); the
-//             input window of taps kx = 1, 2 is the staged row shifted by one
-//             or two pixels in registers.  A block sums a run of tiles and
-//             writes partial sums [split][Cout][9 Cin + 1] (bias last).
-//   k_wreduce sums the partials over splits in a fixed order.
+//   k_dconv      forward (BF16 input; bias, ReLU, BF16 output) and
+//                backward-data (output gradient times the ReLU mask, rounded
+//                to BF16 while staging; FP32 output; optionally that BF16
+//                operand too, for the weight gradient).  The staged operand
+//                has Kc channels (a multiple of 32, or the 8 of the padded
+//                network input), the output Nc (a multiple of 32).  Weights
+//                [Nc][9][Kc]: the forward W, or for backward-data its
+//                flipped transpose.
+//   k_dwgrad     weight and bias gradient.  Both operands are staged
+//                transposed (pixels contiguous, the reduction dimension of
+//                the MFMA); the input window of taps kx = 1, 2 is the staged
+//                row shifted by one or two pixels in registers.  A block sums
+//                a run of tiles and writes partial sums [split][Cout][9 Cin + 1]
+//                (bias last).
+//   k_wreduce    sums weight-gradient partials over splits in a fixed order;
+//   k_bias_fold  folds per-row bias sums where several rows share a bias.
+//   k_upfwd      2x2 stride-2 transposed convolution, forward.
 //
 // Lane layout of the MFMA (as in ws_kernels.hpp): lane l holds
 // A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16] and receives
@@ -318,8 +325,9 @@ constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
 // Block (split, 32 output channels, 16 HW input channels; HW = 1 for the
 // padded network input, whose channels 8..15 are staged as zeros), 2 HW
 // waves.  Wave w: output channels 16 (w & 1), input channels 16 (w >> 1), all
-// nine taps; K = the 32 pixels of one tile row.  The output-gradient tile
-// (the FP32 operand) is staged once for all 16 HW input channels.
+// nine taps; K = the 32 pixels of one tile row.  The output-gradient tile is
+// staged once for all 16 HW input channels: read as the BF16 operand the
+// data gradient left (DPRE), or as the FP32 gradient and the ReLU mask.
 template <bool C8, int HW, bool DPRE>
 __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   constexpr int CI = 16 * HW, NTH = 128 * HW;
