@@ -1,7 +1,7 @@
 // ws_direct.hpp -- direct kernels of the warm-start U-Net on
 // v_mfma_f32_16x16x32_bf16: 3x3 convolutions (stride 1, zero padding 1) of
 // images whose width is a multiple of 32 and height a multiple of 8, and the
-// up-sampling forward of rows of whole 32-pixel segments.
+// up-sampling forward and weight gradient of rows of whole 32-pixel segments.
 //
 // A convolution block works through a run of 8 x 32 pixel tiles of one
 // image.  It stages each tile and its one-pixel halo in LDS once per
@@ -25,7 +25,9 @@
 //                (bias last).
 //   k_wreduce    sums weight-gradient partials over splits in a fixed order;
 //   k_bias_fold  folds per-row bias sums where several rows share a bias.
-//   k_upfwd      2x2 stride-2 transposed convolution, forward.
+//   k_upfwd      2x2 stride-2 transposed convolution, forward;
+//   k_upwgrad    its weight and bias gradient, staged transposed like
+//                k_dwgrad, partial sums [split][4 Cout][Cin + 1].
 //
 // Lane layout of the MFMA (as in ws_kernels.hpp): lane l holds
 // A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16] and receives
@@ -460,6 +462,134 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
       for (int tap = 0; tap < 9; ++tap) row[tap * P.Cin + ci] = acc[tap][q];
     }
     if (h == 0 && blockIdx.z == 0 && l16 == 0) row[Kw] = accb[q];
+  }
+}
+
+// Weight and bias gradient of the up-sampling, for input rows of whole
+// 32-pixel segments:  dW[d][co][ci] = sum_p dOut[up(p,d), co] in[p, ci] over
+// input pixels p, db[co] = sum over d and p of dOut[up(p,d), co].  A block
+// (split, 32 output channels of one parity d, 16 HW input channels; 2 HW
+// waves) sums a run of items of 128 input pixels (four segments), both
+// operands staged transposed (pixels contiguous, the MFMA's reduction
+// dimension) as in k_dwgrad, the next item's loads issued before the current
+// MFMAs.  Partials [split][4 Cout][Cin + 1]: row d Cout + co, the last column
+// the row's bias sum (folded over d by k_bias_fold).
+struct DUpW {
+  Img g;                   // input image
+  int segs, nseg;          // 32-pixel segments per row, in all
+  int ipb;                 // items (4 segments) per split
+  View<const float> dout;  // gradient of the output image (Cout channels)
+  View<const bf16> in;     // input (Cin channels)
+  int Cin, Cout;
+  float *partial;
+};
+constexpr int UW_K = 128, UW_P = UW_K + 8;  // input pixels per item; LDS pitch (bf16)
+
+template <int HW>
+__global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
+  constexpr int CI = 16 * HW, NTH = 128 * HW;
+  constexpr int AN = UW_K / 2 * 4, AIT = (AN + NTH - 1) / NTH;  // pixel pairs x 8-channel chunks
+  constexpr int BNI = UW_K / 2 * (CI / 8), BIT = (BNI + NTH - 1) / NTH;
+  __shared__ __attribute__((aligned(16))) bf16 As[32 * UW_P];  // dOut^T [co][px]
+  __shared__ __attribute__((aligned(16))) bf16 Bs[CI * UW_P];  // in^T [ci][px]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  const int mt = wave & 1, h = wave >> 1;
+  const int cot = P.Cout / 32, d = blockIdx.y / cot, co0 = (blockIdx.y % cot) * 32, ci0 = blockIdx.z * CI;
+  const int H = P.g.H, W = P.g.W, z = blockIdx.x;
+  const int items_total = (P.nseg + 3) / 4;
+  const int i0 = z * P.ipb, i1 = min(items_total, i0 + P.ipb);
+  f4 acc = f4{0.f, 0.f, 0.f, 0.f}, accb = acc;
+  bf16x8 ones;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
+  float4 ga[AIT][4];
+  bf16x8 ib[BIT][2];
+  // input pixel k (0..127) of item it: its segment, row and column; -1 if past the last segment
+  auto pixel = [&](int it, int k, int &row, int &x) {
+    const int sg = it * 4 + k / 32;
+    if (sg >= P.nseg) return false;
+    row = sg / P.segs;
+    x = (sg - row * P.segs) * 32 + k % 32;
+    return true;
+  };
+  auto gload = [&](int it) {
+#pragma unroll
+    for (int a = 0; a < AIT; ++a) {
+      const int q = tid + NTH * a;
+      const int cq = q & 3, k = 2 * (q >> 2);
+      int row, x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ga[a][e] = float4{0.f, 0.f, 0.f, 0.f};
+      if (q < AN && pixel(it, k, row, x)) {
+        const int y = row % H, b = row / H;
+        const size_t Yr = ((size_t)b * 2 * H + 2 * y + (d >> 1)) * 2 * W + (d & 1);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float4 *s = reinterpret_cast<const float4 *>(P.dout.p + (Yr + 2 * (x + e)) * P.dout.cs + P.dout.coff +
+                                                             co0 + 8 * cq);
+          ga[a][2 * e] = s[0];
+          ga[a][2 * e + 1] = s[1];
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < BIT; ++a) {
+      const int q = tid + NTH * a;
+      const int cq = q % (CI / 8), k = 2 * (q / (CI / 8));
+      int row, x;
+      ib[a][0] = ib[a][1] = zero8();
+      if (q < BNI && pixel(it, k, row, x)) {
+        const bf16 *s = P.in.p + ((size_t)row * W + x) * P.in.cs + P.in.coff + ci0 + 8 * cq;
+        ib[a][0] = *reinterpret_cast<const bf16x8 *>(s);
+        ib[a][1] = *reinterpret_cast<const bf16x8 *>(s + P.in.cs);
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int a = 0; a < AIT; ++a) {
+      const int q = tid + NTH * a;
+      if (q < AN) {
+        const int cq = q & 3, k = 2 * (q >> 2);
+        const float f0[8] = {ga[a][0].x, ga[a][0].y, ga[a][0].z, ga[a][0].w, ga[a][1].x, ga[a][1].y, ga[a][1].z, ga[a][1].w};
+        const float f1[8] = {ga[a][2].x, ga[a][2].y, ga[a][2].z, ga[a][2].w, ga[a][3].x, ga[a][3].y, ga[a][3].z, ga[a][3].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * UW_P + k]) = pack_bf16((bf16)f0[j], (bf16)f1[j]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < BIT; ++a) {
+      const int q = tid + NTH * a;
+      if (q < BNI) {
+        const int cq = q % (CI / 8), k = 2 * (q / (CI / 8));
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          *reinterpret_cast<uint32_t *>(&Bs[(8 * cq + j) * UW_P + k]) = pack_bf16(ib[a][0][j], ib[a][1][j]);
+      }
+    }
+  };
+  if (i0 < i1) gload(i0);
+  for (int it = i0; it < i1; ++it) {
+    __syncthreads();  // the previous item's reads are done
+    lstore();
+    __syncthreads();
+    if (it + 1 < i1) gload(it + 1);
+#pragma unroll
+    for (int ks = 0; ks < UW_K / 32; ++ks) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[(16 * mt + l16) * UW_P + 32 * ks + 8 * g]);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[(16 * h + l16) * UW_P + 32 * ks + 8 * g]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      if (h == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb, 0, 0, 0);
+    }
+  }
+  const int ci = ci0 + 16 * h + l16;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = d * P.Cout + co0 + 16 * mt + 4 * g + q;
+    float *row = P.partial + ((size_t)z * 4 * P.Cout + m) * (P.Cin + 1);
+    if (ci < P.Cin) row[ci] = acc[q];
+    if (h == 0 && blockIdx.z == 0 && l16 == 0) row[P.Cin] = accb[q];
   }
 }
 

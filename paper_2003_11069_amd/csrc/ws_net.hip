@@ -476,8 +476,40 @@ int up_fwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<bf16> out)
   return WS_OK;
 }
 
+// Direct up-sampling weight gradient: input rows of whole 32-pixel segments,
+// Cout and Cin multiples of 32.  Split plan: about 4096 waves in all.
+bool up_direct_wgrad(const ws_net *n, const Img &gin, const Up &u) {
+  return n->cfg.conv_algo == 0 && gin.W % 32 == 0 && u.Cout % 32 == 0 && u.Cin % 32 == 0;
+}
+void up_wplan(const Img &gin, const Up &u, int &hw, int &splits, int &ipb) {
+  hw = u.Cin % 64 == 0 ? 4 : 2;
+  const int items = (gin.B * gin.H * (gin.W / 32) + 3) / 4;
+  const int combos = 4 * (u.Cout / 32) * (u.Cin / (16 * hw));
+  const int want = std::max(1, 4096 / (2 * hw) / combos);  // 2048, 8192, 16384 waves measured slower
+  ipb = std::max(1, (items + want - 1) / want);
+  splits = (items + ipb - 1) / ipb;
+}
+
 int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const float> dout, View<float> din) {
   const int P = gin.B * gin.H * gin.W;
+  if (up_direct_wgrad(n, gin, u)) {
+    DUpW pw{};
+    pw.g = gin;
+    pw.segs = gin.W / 32;
+    pw.nseg = gin.B * gin.H * pw.segs;
+    pw.dout = dout;
+    pw.in = in;
+    pw.Cin = u.Cin;
+    pw.Cout = u.Cout;
+    pw.partial = n->scratch;
+    int hw, splits;
+    up_wplan(gin, u, hw, splits, pw.ipb);
+    if ((size_t)splits * 4 * u.Cout * (u.Cin + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+    const dim3 grid((unsigned)splits, (unsigned)(4 * u.Cout / 32), (unsigned)(u.Cin / (16 * hw)));
+    if (hw == 4) hipLaunchKernelGGL(k_upwgrad<4>, grid, dim3(512), 0, n->stream, pw);
+    else hipLaunchKernelGGL(k_upwgrad<2>, grid, dim3(256), 0, n->stream, pw);
+    launch_split_reduce(n, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
+  } else {
   int splits, chunk;
   split_plan(P, 4 * u.Cout, u.Cin + 1, splits, chunk);
   if ((size_t)splits * 4 * u.Cout * (u.Cin + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
@@ -492,6 +524,7 @@ int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const floa
   pw.dCout = Div::make(u.Cout);
   gemm(n, pw, 4 * u.Cout, u.Cin + 1, splits, pick_tile_split(4 * u.Cout, u.Cin + 1));
   launch_split_reduce(n, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
+  }
   UpBwdData pd;
   pd.g = gin;
   pd.dout = dout;
@@ -707,6 +740,12 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
         conv(l, n->d1[l]);
         conv(l, n->d2[l]);
         need(l + 1, 4 * n->up[l].Cout, n->up[l].Cin + 1);  // over the input (coarser) pixels
+        const Img gu = Img::make(B, imgH(n, l + 1), imgW(n, l + 1));
+        if (up_direct_wgrad(n, gu, n->up[l])) {
+          int hw, splits, ipb;
+          up_wplan(gu, n->up[l], hw, splits, ipb);
+          worst = std::max(worst, (size_t)splits * 4 * n->up[l].Cout * (n->up[l].Cin + 1));
+        }
       }
     }
     conv(0, n->head);
