@@ -39,9 +39,10 @@
  *
  * Numerics: activations are stored in BF16 (every layer output is rounded to
  * BF16 after bias and ReLU; the head output stays FP32); weights enter the
- * MFMA as BF16 copies of the FP32 masters; backward operands (output
- * gradients times the ReLU mask) are rounded to BF16; products accumulate in
- * FP32; gradients are stored in FP32; weight-gradient sums over pixels are
+ * MFMA as BF16 copies of the FP32 masters; gradients of activations are
+ * stored in BF16 (each is rounded once, where it is produced, and every
+ * consumer takes it, times the ReLU mask, as a BF16 MFMA operand); products
+ * accumulate in FP32; weight gradients are FP32; weight-gradient sums over pixels are
  * split in fixed chunks and reduced in a fixed order, so results are
  * deterministic.  The loss is accumulated in FP64.
  *

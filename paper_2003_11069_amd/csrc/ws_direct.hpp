@@ -10,9 +10,9 @@
 // backward operand once per tap).
 //
 //   k_dconv      forward (BF16 input; bias, ReLU, BF16 output) and
-//                backward-data (output gradient times the ReLU mask, rounded
-//                to BF16 while staging; FP32 output; optionally that BF16
-//                operand too, for the weight gradient).  The staged operand
+//                backward-data (BF16 output gradient times the ReLU mask
+//                while staging; BF16 output; optionally that masked operand
+//                too, for the weight gradient).  The staged operand
 //                has Kc channels (a multiple of 32, or the 8 of the padded
 //                network input), the output Nc (a multiple of 32).  Weights
 //                [Nc][9][Kc]: the forward W, or for backward-data its
@@ -71,13 +71,13 @@ struct DConv {
   DTiles T;
   int tpb;               // tiles per block (block b runs tiles b tpb ..)
   View<const bf16> x;    // forward: input activations (Kc channels)
-  View<const float> dx;  // backward-data: output gradient of the layer (Kc channels)
+  View<const bf16> dx;   // backward-data: output gradient of the layer (Kc channels)
   View<const bf16> act;  // backward-data: the layer's output (ReLU mask)
   int Kc, Nc;
   const bf16 *Wk;        // [Nc][9][Kc]
   const float *bias;     // forward
   View<bf16> y;          // forward output (Nc channels)
-  View<float> dy;        // backward-data output (stored, not added)
+  View<bf16> dy;         // backward-data output (stored, not added)
   bf16 *dpre;            // backward-data: when set, the BF16 operand (output
                          // gradient x mask) of every tile's own pixels is
                          // also written here, [pixel][Kc], for the weight
@@ -157,13 +157,13 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
     }
   };
   auto gload = [&](int item) {
-    float4 xg[BWD ? XIT : 1][2];
+    bf16x8 xg[BWD ? XIT : 1];
     const int t = t0 + item / slices, s = item % slices;
     int b, y0, x0;
     P.T.at(t, b, y0, x0);
     const int64_t tb = (int64_t)(b * H + y0) * W + x0;  // the tile's first pixel
     const bf16 *xb = P.x.p + tb * P.x.cs + P.x.coff + s * 32;
-    const float *db = P.dx.p + tb * P.dx.cs + P.dx.coff + s * 32;
+    const bf16 *db = P.dx.p + tb * P.dx.cs + P.dx.coff + s * 32;
     const bf16 *ab = P.act.p + tb * P.act.cs + P.act.coff + s * 32;
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
@@ -172,25 +172,20 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       const int yy = y0 + rr - 1, xx = x0 + pix - rr * DW - 1;
       const bool in = q < XN && yy >= 0 && yy < H && xx >= 0 && xx < W;
       if (BWD) {
-        xg[it][0] = xg[it][1] = float4{0.f, 0.f, 0.f, 0.f};
-        xa[it] = zero8();
+        xg[it] = xa[it] = zero8();
         if (in) {
-          const float4 *d = reinterpret_cast<const float4 *>(db + rel[it] * P.dx.cs + ch);
-          xg[it][0] = d[0];
-          xg[it][1] = d[1];
+          xg[it] = *reinterpret_cast<const bf16x8 *>(db + rel[it] * P.dx.cs + ch);
           xa[it] = *reinterpret_cast<const bf16x8 *>(ab + rel[it] * P.act.cs + ch);
         }
       } else {
         xa[it] = in ? *reinterpret_cast<const bf16x8 *>(xb + rel[it] * P.x.cs + ch) : zero8();
       }
     }
-    if (BWD) {  // output gradient times the ReLU mask, rounded to BF16
+    if (BWD) {  // output gradient times the ReLU mask
 #pragma unroll
       for (int it = 0; it < XIT; ++it) {
-        const float f[8] = {xg[it][0].x, xg[it][0].y, xg[it][0].z, xg[it][0].w,
-                            xg[it][1].x, xg[it][1].y, xg[it][1].z, xg[it][1].w};
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xa[it][j] = (bf16)((float)xa[it][j] > 0.f ? f[j] : 0.f);
+        for (int j = 0; j < 8; ++j) xa[it][j] = (float)xa[it][j] > 0.f ? xg[it][j] : (bf16)0.f;
       }
       if (P.dpre && n0 == 0) {  // the tile's own pixels, for the weight gradient
 #pragma unroll
@@ -257,7 +252,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
     // loads here: they would wait for the prefetch)
     int b, y0, x0;
     P.T.at(t0 + item / slices, b, y0, x0);
-    if (BWD || NW > 1) {
+    if (NW > 1) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = 2 * rg + (i >> 1);
@@ -269,7 +264,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
             const int col = 16 * (i & 1) + 4 * g + q;
             const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
             if (BWD) {
-              P.dy.p[p * P.dy.cs + P.dy.coff + n] = acc[i][j][q];
+              P.dy.p[p * P.dy.cs + P.dy.coff + n] = (bf16)acc[i][j][q];
             } else {
               const float r = acc[i][j][q] + bias[j];
               P.y.p[p * P.y.cs + P.y.coff + n] = (bf16)(r > 0.f ? r : 0.f);
@@ -279,8 +274,9 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
         }
       }
     } else {
-      // BF16 results through LDS (each wave's 64 pixels x 32 channels in its
-      // own part of Xs, pixel pitch OP), then 16-byte stores
+      // BF16 results (forward: with bias and ReLU) through LDS (each wave's
+      // 64 pixels x 32 channels in its own part of Xs, pixel pitch OP), then
+      // 16-byte stores
       __syncthreads();  // every wave is done reading Xs for this item
       bf16 *O = Xs + wave * 64 * OP;
 #pragma unroll
@@ -290,7 +286,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const float r = acc[i][j][q] + bias[j];
-            O[(32 * (i >> 1) + 16 * (i & 1) + 4 * g + q) * OP + 16 * j + l16] = (bf16)(r > 0.f ? r : 0.f);
+            O[(32 * (i >> 1) + 16 * (i & 1) + 4 * g + q) * OP + 16 * j + l16] = (bf16)(BWD ? r : r > 0.f ? r : 0.f);
           }
           acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
@@ -300,8 +296,8 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
         const int e = lane + 64 * k, px = e / 4, c8 = (e - px * 4) * 8;
         const int row = 2 * rg + px / 32, col = px % 32;
         const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
-        *reinterpret_cast<bf16x8 *>(P.y.p + p * P.y.cs + P.y.coff + n0 + c8) =
-            *reinterpret_cast<const bf16x8 *>(&O[px * OP + c8]);
+        const View<bf16> &Y = BWD ? P.dy : P.y;
+        *reinterpret_cast<bf16x8 *>(Y.p + p * Y.cs + Y.coff + n0 + c8) = *reinterpret_cast<const bf16x8 *>(&O[px * OP + c8]);
       }
     }
   }
@@ -312,7 +308,7 @@ struct DWGrad {
   Img g;
   DTiles T;
   int tps;                 // tiles per split (split z sums tiles z tps ..)
-  View<const float> dout;  // output gradient of the layer (Cout channels)
+  View<const bf16> dout;   // output gradient of the layer (Cout channels)
   View<const bf16> act;    // the layer's output (ReLU mask)
   View<const bf16> in;     // the layer's input (Cin channels)
   int Cin, Cout;
@@ -329,7 +325,7 @@ constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
 // waves.  Wave w: output channels 16 (w & 1), input channels 16 (w >> 1), all
 // nine taps; K = the 32 pixels of one tile row.  The output-gradient tile is
 // staged once for all 16 HW input channels: read as the BF16 operand the
-// data gradient left (DPRE), or as the FP32 gradient and the ReLU mask.
+// data gradient left (DPRE), or as the gradient and the ReLU mask.
 template <bool C8, int HW, bool DPRE>
 __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   constexpr int CI = 16 * HW, NTH = 128 * HW;
@@ -348,10 +344,10 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   const int z = blockIdx.x;
   const int tb = z * P.tps, te = min(P.T.n, tb + P.tps);
   // staging registers of one tile: output gradient (two pixels x 8 channels
-  // per item: FP32 values and the mask), input (two pixels x 8 channels)
+  // per item: the gradient and the mask), input (two pixels x 8 channels)
   constexpr int AN = DT_H * DT_W / 2 * 4, AIT = AN / NTH;
   constexpr int NCH = CI / 8, BN_ = DH * (DW / 2) * NCH, BIT = (BN_ + NTH - 1) / NTH;
-  float4 ga[DPRE ? 1 : AIT][4];
+  bf16x8 ga[DPRE ? 1 : AIT][2];
   bf16x8 ma[AIT][2], ib[BIT][2];  // DPRE: ma holds the BF16 operand itself
   auto gload = [&](int t) {
     int b, y0, x0;
@@ -367,9 +363,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
         if constexpr (DPRE) {
           ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.dpre + o * P.Cout + co0 + 8 * cq);
         } else {
-          const float4 *d = reinterpret_cast<const float4 *>(P.dout.p + o * P.dout.cs + P.dout.coff + co0 + 8 * cq);
-          ga[it][2 * e] = d[0];
-          ga[it][2 * e + 1] = d[1];
+          ga[it][e] = *reinterpret_cast<const bf16x8 *>(P.dout.p + o * P.dout.cs + P.dout.coff + co0 + 8 * cq);
           ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.act.p + o * P.act.cs + P.act.coff + co0 + 8 * cq);
         }
       }
@@ -399,10 +393,8 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[e][j] = ma[it][e][j];
         } else {
-          const float f[8] = {ga[it][2 * e].x, ga[it][2 * e].y, ga[it][2 * e].z, ga[it][2 * e].w,
-                              ga[it][2 * e + 1].x, ga[it][2 * e + 1].y, ga[it][2 * e + 1].z, ga[it][2 * e + 1].w};
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[e][j] = (bf16)((float)ma[it][e][j] > 0.f ? f[j] : 0.f);
+          for (int j = 0; j < 8; ++j) v[e][j] = (float)ma[it][e][j] > 0.f ? ga[it][e][j] : (bf16)0.f;
         }
       }
 #pragma unroll
@@ -478,7 +470,7 @@ struct DUpW {
   Img g;                   // input image
   int segs, nseg;          // 32-pixel segments per row, in all
   int ipb;                 // items (4 segments) per split
-  View<const float> dout;  // gradient of the output image (Cout channels)
+  View<const bf16> dout;   // gradient of the output image (Cout channels)
   View<const bf16> in;     // input (Cin channels)
   int Cin, Cout;
   float *partial;
@@ -502,8 +494,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
   bf16x8 ones;
 #pragma unroll
   for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
-  float4 ga[AIT][4];
-  bf16x8 ib[BIT][2];
+  bf16x8 ga[AIT][2], ib[BIT][2];
   // input pixel k (0..127) of item it: its segment, row and column; -1 if past the last segment
   auto pixel = [&](int it, int k, int &row, int &x) {
     const int sg = it * 4 + k / 32;
@@ -518,18 +509,14 @@ __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
       const int q = tid + NTH * a;
       const int cq = q & 3, k = 2 * (q >> 2);
       int row, x;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) ga[a][e] = float4{0.f, 0.f, 0.f, 0.f};
+      ga[a][0] = ga[a][1] = zero8();
       if (q < AN && pixel(it, k, row, x)) {
         const int y = row % H, b = row / H;
         const size_t Yr = ((size_t)b * 2 * H + 2 * y + (d >> 1)) * 2 * W + (d & 1);
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const float4 *s = reinterpret_cast<const float4 *>(P.dout.p + (Yr + 2 * (x + e)) * P.dout.cs + P.dout.coff +
-                                                             co0 + 8 * cq);
-          ga[a][2 * e] = s[0];
-          ga[a][2 * e + 1] = s[1];
-        }
+        for (int e = 0; e < 2; ++e)
+          ga[a][e] = *reinterpret_cast<const bf16x8 *>(P.dout.p + (Yr + 2 * (x + e)) * P.dout.cs + P.dout.coff + co0 +
+                                                       8 * cq);
       }
     }
 #pragma unroll
@@ -551,11 +538,9 @@ __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
       const int q = tid + NTH * a;
       if (q < AN) {
         const int cq = q & 3, k = 2 * (q >> 2);
-        const float f0[8] = {ga[a][0].x, ga[a][0].y, ga[a][0].z, ga[a][0].w, ga[a][1].x, ga[a][1].y, ga[a][1].z, ga[a][1].w};
-        const float f1[8] = {ga[a][2].x, ga[a][2].y, ga[a][2].z, ga[a][2].w, ga[a][3].x, ga[a][3].y, ga[a][3].z, ga[a][3].w};
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * UW_P + k]) = pack_bf16((bf16)f0[j], (bf16)f1[j]);
+          *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * UW_P + k]) = pack_bf16(ga[a][0][j], ga[a][1][j]);
       }
     }
 #pragma unroll
@@ -657,7 +642,7 @@ static __global__ __launch_bounds__(64 * WR_G) void k_wreduce(const float *parti
 //   out[(2y+dy, 2x+dx), co] = b[co] + sum_ci W[d][co][ci] in[(y,x), ci]
 // for the segment's 32 pixels and all Cout channels and writes them as
 // 16-byte rows through LDS.  (A direct data gradient, with each wave loading
-// its FP32 operand itself, measured slower than the implicit GEMM, which
+// its operand itself, measured slower than the implicit GEMM, which
 // stages it once per block: 18.5 -> 41 us at level 0; it is not used.)
 struct DUp {
   Img g;                  // input image

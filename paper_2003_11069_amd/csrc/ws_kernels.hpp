@@ -9,7 +9,9 @@
 //
 // Layout: activations NHWC BF16 with an explicit channel stride and offset
 // (a decoder input is one buffer holding [up-sampled | skip] channels),
-// gradients NHWC FP32, weights BF16 copies of FP32 master parameters.
+// gradients of activations NHWC BF16 (every consumer takes them as a BF16
+// MFMA operand; only the pooling backward adds two of them), weights BF16
+// copies of FP32 master parameters, weight gradients FP32.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -252,38 +254,32 @@ struct ConvFwd {
   }
 };
 
-// Gradient operand of a layer output: dOut (FP32) times the ReLU mask of the
-// forward output (act > 0), rounded to BF16 for the MFMA.
+// Gradient operand of a layer output: dOut (BF16) times the ReLU mask of the
+// forward output (act > 0).
 template <bool RELU>
-__device__ __forceinline__ bf16x8 grad8(const View<const float> &d, const View<const bf16> &act, int q, int c) {
-  const float4 *s = reinterpret_cast<const float4 *>(d.p + (size_t)q * d.cs + d.coff + c);
-  const float4 lo = s[0], hi = s[1];
-  const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-  bf16x8 r;
+__device__ __forceinline__ bf16x8 grad8(const View<const bf16> &d, const View<const bf16> &act, int q, int c) {
+  bf16x8 r = *reinterpret_cast<const bf16x8 *>(d.p + (size_t)q * d.cs + d.coff + c);
   if (RELU) {
     const bf16x8 a = *reinterpret_cast<const bf16x8 *>(act.p + (size_t)q * act.cs + act.coff + c);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) r[j] = (bf16)((float)a[j] > 0.f ? v[j] : 0.f);
-  } else {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) r[j] = (bf16)v[j];
+    for (int j = 0; j < 8; ++j) r[j] = (float)a[j] > 0.f ? r[j] : (bf16)0.f;
   }
   return r;
 }
 
 // Backward-data of ConvFwd: dIn[p, ci] = sum_{ky,kx,co} WtT[ci][(ky*KS+kx)*Cout + co]
 //   dPre[p + (ky-r, kx-r), co],  WtT = weights flipped in (ky,kx) and transposed.
-// M = pixels, N = Cin, K = KS*KS*Cout (Cout multiple of 8).  Writes FP32.
+// M = pixels, N = Cin, K = KS*KS*Cout (Cout multiple of 8).  Writes BF16.
 template <int KS, bool RELU>
 struct ConvBwdData {
   static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
   Img g;
-  View<const float> dout;
+  View<const bf16> dout;
   View<const bf16> act;  // forward output (ReLU mask)
   int Cin, Cout;
   Div dCout;
   const bf16 *WtT;  // [Cin][K]
-  View<float> din;
+  View<bf16> din;
   __device__ __forceinline__ int K() const { return KS * KS * Cout; }
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = K(); }
   __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
@@ -301,8 +297,7 @@ struct ConvBwdData {
   }
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     if (m >= g.P() || n >= Cin) return;
-    float *d = din.p + (size_t)m * din.cs + din.coff + n;
-    *d = v;
+    din.p[(size_t)m * din.cs + din.coff + n] = (bf16)v;
   }
 };
 
@@ -316,7 +311,7 @@ template <int KS, bool RELU, bool TR = false>
 struct ConvBwdWeight {
   static constexpr int A_LAYOUT = COL, B_LAYOUT = COL;
   Img g;
-  View<const float> dout;
+  View<const bf16> dout;
   View<const bf16> act;
   View<const bf16> in;
   int Cin, Cout;
@@ -400,29 +395,21 @@ __device__ __forceinline__ int up_pixel(const Img &g, int p, int d) {
   return (b * 2 * g.H + 2 * y + (d >> 1)) * 2 * g.W + 2 * x + (d & 1);
 }
 
-__device__ __forceinline__ bf16x8 f32x8_to_bf16(const float *s) {
-  const float4 lo = reinterpret_cast<const float4 *>(s)[0], hi = reinterpret_cast<const float4 *>(s)[1];
-  bf16x8 v;
-  v[0] = (bf16)lo.x; v[1] = (bf16)lo.y; v[2] = (bf16)lo.z; v[3] = (bf16)lo.w;
-  v[4] = (bf16)hi.x; v[5] = (bf16)hi.y; v[6] = (bf16)hi.z; v[7] = (bf16)hi.w;
-  return v;
-}
-
 // Backward-data of UpFwd: dIn[p, ci] = sum_{d,co} WtT[ci][d*Cout + co] dOut[up(p,d), co].
 // M = Pin, N = Cin, K = 4 Cout.  No activation on the up-sampling output.
 struct UpBwdData {
   static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
   Img g;
-  View<const float> dout;  // output-image gradient
+  View<const bf16> dout;  // output-image gradient
   int Cin, Cout;
   Div dCout;
   const bf16 *WtT;  // [Cin][4][Cout]
-  View<float> din;
+  View<bf16> din;
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = 4 * Cout; }
   __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
     if (m >= g.P() || k >= kend) return zero8();
     const int d = (int)dCout.q((uint32_t)k), co = k - d * Cout;
-    return f32x8_to_bf16(dout.p + (size_t)up_pixel(g, m, d) * dout.cs + dout.coff + co);
+    return *reinterpret_cast<const bf16x8 *>(dout.p + (size_t)up_pixel(g, m, d) * dout.cs + dout.coff + co);
   }
   __device__ __forceinline__ bf16x8 b(int n, int k, int kend, int) const {
     if (n >= Cin || k >= kend) return zero8();
@@ -430,7 +417,7 @@ struct UpBwdData {
   }
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     if (m >= g.P() || n >= Cin) return;
-    din.p[(size_t)m * din.cs + din.coff + n] = v;
+    din.p[(size_t)m * din.cs + din.coff + n] = (bf16)v;
   }
 };
 
@@ -440,7 +427,7 @@ struct UpBwdData {
 struct UpBwdWeight {
   static constexpr int A_LAYOUT = COL, B_LAYOUT = COL;
   Img g;
-  View<const float> dout;
+  View<const bf16> dout;
   View<const bf16> in;
   int Cin, Cout;
   Div dCout;
@@ -453,7 +440,7 @@ struct UpBwdWeight {
   __device__ __forceinline__ bf16x8 a(int m, int p, int kend, int) const {
     if (p >= kend || m >= 4 * Cout) return zero8();
     const int d = (int)dCout.q((uint32_t)m), co = m - d * Cout;
-    return f32x8_to_bf16(dout.p + (size_t)up_pixel(g, p, d) * dout.cs + dout.coff + co);
+    return *reinterpret_cast<const bf16x8 *>(dout.p + (size_t)up_pixel(g, p, d) * dout.cs + dout.coff + co);
   }
   __device__ __forceinline__ bf16x8 b(int n, int p, int kend, int) const {
     bf16x8 v = zero8();
@@ -513,8 +500,8 @@ static __global__ __launch_bounds__(256) void k_pool_fwd(Img g, View<const bf16>
 // Backward: a thread per pooled element (consecutive threads take consecutive
 // channels, so the read-modify-write of the maximum's element is coalesced;
 // 8-channel vectors measured slower here).
-static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16> in, int C, View<const float> dout,
-                                                  View<float> din) {
+static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16> in, int C, View<const bf16> dout,
+                                                  View<bf16> din) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int Ho = g.H / 2, Wo = g.W / 2;
   if (i >= g.B * Ho * Wo * C) return;
@@ -527,7 +514,8 @@ static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16>
     if (v > best) { best = v; arg = d; }
   }
   const size_t q = ((size_t)b * g.H + 2 * y + (arg >> 1)) * g.W + 2 * x + (arg & 1);
-  din.p[q * din.cs + din.coff + c] += dout.p[(size_t)t * dout.cs + dout.coff + c];
+  bf16 &d = din.p[q * din.cs + din.coff + c];
+  d = (bf16)((float)d + (float)dout.p[(size_t)t * dout.cs + dout.coff + c]);
 }
 
 // Network input: FP32 NHWC [P][cin] -> BF16 [P][8] (channels padded with
@@ -543,8 +531,8 @@ static __global__ __launch_bounds__(256) void k_pack_input(const float *x, int P
 
 // MSE over the first `cout` channels of the head output (8 channels per
 // pixel), a pixel per thread: per-block partial sums (the pixel's channels in
-// order, then a fixed tree) and dY = 2 (y - t) / (P cout), zero padding.
-static __global__ __launch_bounds__(256) void k_mse(const float *y, const float *t, int P, int cout, float *dy,
+// order, then a fixed tree) and dY = 2 (y - t) / (P cout) stored as BF16, zero padding.
+static __global__ __launch_bounds__(256) void k_mse(const float *y, const float *t, int P, int cout, bf16 *dy,
                                              double *partial) {
   __shared__ double sh[256];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -563,9 +551,10 @@ static __global__ __launch_bounds__(256) void k_mse(const float *y, const float 
         gv[c] = 2.f * d / (float)((double)P * cout);
       }
     }
-    float4 *ds = reinterpret_cast<float4 *>(dy + (size_t)p * 8);
-    ds[0] = float4{gv[0], gv[1], gv[2], gv[3]};
-    ds[1] = float4{gv[4], gv[5], gv[6], gv[7]};
+    bf16x8 gb;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) gb[c] = (bf16)gv[c];
+    *reinterpret_cast<bf16x8 *>(dy + (size_t)p * 8) = gb;
   }
   sh[threadIdx.x] = e;
   __syncthreads();

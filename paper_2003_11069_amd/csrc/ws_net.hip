@@ -90,8 +90,8 @@ struct ws_net {
   std::vector<Buf<bf16>> mid_e, cat, mid_d, dec;
   Buf<bf16> bott;                // encoder output of the last level
   Buf<float> y;                  // head output, 8 channels
-  std::vector<Buf<float>> dpool, dmid_e, dcat, dmid_d, ddec;
-  Buf<float> dbott, dy;
+  std::vector<Buf<bf16>> dpool, dmid_e, dcat, dmid_d, ddec;  // activation gradients (BF16)
+  Buf<bf16> dbott, dy;
   float *scratch = nullptr;  // split-K partials
   float *bias_rows = nullptr;  // per-row bias sums of an up-sampling weight gradient
   bf16 *dpre = nullptr;        // BF16 backward operand of a layer, data gradient -> weight gradient
@@ -351,7 +351,7 @@ void launch_split_reduce(ws_net *n, int splits, int M, int Kw, float *dW, float 
 
 template <int KS, bool RELU, bool TR>
 void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act,
-                     View<const float> dout, int chunk, int splits, const WShape &ws) {
+                     View<const bf16> dout, int chunk, int splits, const WShape &ws) {
   ConvBwdWeight<KS, RELU, TR> pw;
   pw.g = g;
   pw.dout = dout;
@@ -367,8 +367,8 @@ void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<
 
 // weight and bias gradients of a conv layer, then (if din.p) its data gradient
 template <int KS, bool RELU>
-int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act, View<const float> dout,
-               View<float> din) {
+int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act, View<const bf16> dout,
+               View<bf16> din) {
   const int P = g.B * g.H * g.W;
   const int Kw = KS * KS * c.Cin;
   const bool wdirect = KS == 3 && RELU && direct_ok(n, g, c.Cin, c.Cout, true);
@@ -490,7 +490,7 @@ void up_wplan(const Img &gin, const Up &u, int &hw, int &splits, int &ipb) {
   splits = (items + ipb - 1) / ipb;
 }
 
-int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const float> dout, View<float> din) {
+int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const bf16> dout, View<bf16> din) {
   const int P = gin.B * gin.H * gin.W;
   if (up_direct_wgrad(n, gin, u)) {
     DUpW pw{};
@@ -591,7 +591,7 @@ int backward(ws_net *n, int B) {
     rc = conv_bwd_t<3, true>(n, n->d1[l], gl, cv(n->cat[l]), cv(n->mid_d[l]), cv(n->dmid_d[l]), mv(n->dcat[l]));
     if (rc) return rc;
     View<const bf16> uin = l == L - 2 ? cv(n->bott) : cv(n->dec[l + 1]);
-    View<float> dup = l == L - 2 ? mv(n->dbott) : mv(n->ddec[l + 1]);
+    View<bf16> dup = l == L - 2 ? mv(n->dbott) : mv(n->ddec[l + 1]);
     rc = up_bwd(n, n->up[l], gu, uin, cv(n->dcat[l], 0), dup);
     if (rc) return rc;
   }
@@ -599,11 +599,11 @@ int backward(ws_net *n, int B) {
     Img g = Img::make(B, imgH(n, l), imgW(n, l));
     const int C = chans(n, l);
     View<const bf16> eout = l < L - 1 ? cv(n->cat[l], C) : cv(n->bott);
-    View<const float> deout = l < L - 1 ? cv(n->dcat[l], C) : cv(n->dbott);
+    View<const bf16> deout = l < L - 1 ? cv(n->dcat[l], C) : cv(n->dbott);
     rc = conv_bwd_t<3, true>(n, n->e2[l], g, cv(n->mid_e[l]), eout, deout, mv(n->dmid_e[l]));
     if (rc) return rc;
     View<const bf16> in = l == 0 ? cv(n->xin) : cv(n->pool[l]);
-    View<float> din = l == 0 ? View<float>{nullptr, 0, 0} : mv(n->dpool[l]);
+    View<bf16> din = l == 0 ? View<bf16>{nullptr, 0, 0} : mv(n->dpool[l]);
     rc = conv_bwd_t<3, true>(n, n->e1[l], g, in, cv(n->mid_e[l]), cv(n->dmid_e[l]), din);
     if (rc) return rc;
     if (l > 0) {  // route the pooled gradient into the level l-1 encoder output
