@@ -419,26 +419,35 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
     __syncthreads();
     if (t + 1 < te) gload(t + 1);
     {
-#pragma unroll 2
-      for (int r = 0; r < DT_H; ++r) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[(16 * mt + l16) * WA_P + r * DT_W + 8 * g]);
-        if (h == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, accb, 0, 0, 0);
+      // each staged input row rr is read once and serves the output rows
+      // r = rr - ky, ky = 0..2 (tap row ky); the three column shifts kx come
+      // from one 16-byte read and the next 4 bytes
+      bf16x8 a[DT_H];
+#pragma unroll
+      for (int rr = 0; rr < DH; ++rr) {
+        if (rr < DT_H) {
+          a[rr] = *reinterpret_cast<const bf16x8 *>(&As[(16 * mt + l16) * WA_P + rr * DT_W + 8 * g]);
+          if (h == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rr], ones, accb, 0, 0, 0);
+        }
+        const bf16 *src = &Bs[(16 * h + l16) * WB_P + rr * WB_R + 8 * g];
+        const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
+        const uint32_t hi = *reinterpret_cast<const uint32_t *>(src + 8);
+        u32x4 s1, s2;  // windows starting one and two pixels further right
+        s1[0] = __builtin_amdgcn_alignbyte(lo[1], lo[0], 2);
+        s1[1] = __builtin_amdgcn_alignbyte(lo[2], lo[1], 2);
+        s1[2] = __builtin_amdgcn_alignbyte(lo[3], lo[2], 2);
+        s1[3] = __builtin_amdgcn_alignbyte(hi, lo[3], 2);
+        s2[0] = lo[1];
+        s2[1] = lo[2];
+        s2[2] = lo[3];
+        s2[3] = hi;
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
-          const bf16 *src = &Bs[(16 * h + l16) * WB_P + (r + ky) * WB_R + 8 * g];
-          const u32x4 lo = *reinterpret_cast<const u32x4 *>(src), hi = *reinterpret_cast<const u32x4 *>(src + 8);
-          u32x4 s1, s2;  // windows starting one and two pixels further right
-          s1[0] = __builtin_amdgcn_alignbyte(lo[1], lo[0], 2);
-          s1[1] = __builtin_amdgcn_alignbyte(lo[2], lo[1], 2);
-          s1[2] = __builtin_amdgcn_alignbyte(lo[3], lo[2], 2);
-          s1[3] = __builtin_amdgcn_alignbyte(hi[0], lo[3], 2);
-          s2[0] = lo[1];
-          s2[1] = lo[2];
-          s2[2] = lo[3];
-          s2[3] = hi[0];
-          acc[3 * ky + 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, lo), acc[3 * ky + 0], 0, 0, 0);
-          acc[3 * ky + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, s1), acc[3 * ky + 1], 0, 0, 0);
-          acc[3 * ky + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, s2), acc[3 * ky + 2], 0, 0, 0);
+          const int r = rr - ky;
+          if (r < 0 || r >= DT_H) continue;
+          acc[3 * ky + 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], __builtin_bit_cast(bf16x8, lo), acc[3 * ky + 0], 0, 0, 0);
+          acc[3 * ky + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], __builtin_bit_cast(bf16x8, s1), acc[3 * ky + 1], 0, 0, 0);
+          acc[3 * ky + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], __builtin_bit_cast(bf16x8, s2), acc[3 * ky + 2], 0, 0, 0);
         }
       }
     }

@@ -253,19 +253,22 @@ bool direct_ok(const ws_net *n, const Img &g, int Kc, int Nc, bool c8_ok) {
 }
 
 // Input channels per direct weight-gradient block (16 HW, 2 HW waves): 16
-// for the padded network input, 32 at 32 channels, else 64 (the FP32
+// for the padded network input, 32 at 32 channels, else 64 (the
 // output-gradient tile is staged once per block, so wider blocks read it
 // fewer times).
 int direct_whw(int Cin) { return Cin == 8 ? 1 : (Cin % 64 == 0 ? 4 : 2); }
 
-// Split plan of a direct weight gradient: about 1536 waves (6 per CU) in
-// all, each block summing a run of tiles.  Fewer splits write and reduce
-// fewer partials; 3072 and 768 waves measured 1.74 and 1.91 ms per training
-// step against 1.69.
+// Split plan of a direct weight gradient, each block summing a run of
+// tiles: 256 blocks of 4 or 8 waves (one per CU: registers and LDS hold one
+// 8-wave block per CU, so every block runs in the first round), 512 of the
+// 2-wave blocks of the padded input.  Measured per training step: 1.45 ms,
+// against 1.51 with 192 / 384 / 768 blocks (hw 4 / 2 / 1; a quarter of the
+// CUs idle), 1.53 with 512 / 768 / 1024 (a second round), 1.48 with 128
+// blocks at hw 2.
 void direct_wplan(int ntiles, int Cin, int Cout, int &splits, int &tps) {
   const int hw = direct_whw(Cin);
   const int combos = std::max(1, Cin / (16 * hw)) * (Cout / 32);
-  const int want = std::max(1, 1536 / (2 * hw) / combos);
+  const int want = std::max(1, (hw == 1 ? 512 : 256) / combos);
   tps = std::max(1, (ntiles + want - 1) / want);
   splits = (ntiles + tps - 1) / tps;
 }
