@@ -23,8 +23,8 @@
 //                row shifted by one or two pixels in registers.  A block sums
 //                a run of tiles and writes partial sums [split][Cout][9 Cin + 1]
 //                (bias last).
-//   k_wreduce    sums weight-gradient partials over splits in a fixed order;
-//   k_bias_fold  folds per-row bias sums where several rows share a bias.
+//   k_wreduce    sums weight-gradient partials over splits in a fixed order,
+//                the partials of several layers in one launch.
 //   k_upfwd      2x2 stride-2 transposed convolution, forward;
 //   k_upwgrad    its weight and bias gradient, staged transposed like
 //                k_dwgrad, partial sums [split][4 Cout][Cin + 1].
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
 // operands staged transposed (pixels contiguous, the MFMA's reduction
 // dimension) as in k_dwgrad, the next item's loads issued before the current
 // MFMAs.  Partials [split][4 Cout][Cin + 1]: row d Cout + co, the last column
-// the row's bias sum (folded over d by k_bias_fold).
+// the row's bias sum (k_wreduce adds those of the four parities).
 struct DUpW {
   Img g;                   // input image
   int segs, nseg;          // 32-pixel segments per row, in all
@@ -587,31 +587,69 @@ __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
   }
 }
 
-// Fixed-order sum of split partials [splits][E] (E = rows (Kw + 1), a
-// multiple of 4) into dW [rows][Kw] and db [rows] (column Kw; per-row bias
-// sums, folded by k_bias_fold where several rows share a bias).  A block sums
-// 256 consecutive elements (a float4 per lane) over 16 split groups (group
-// g adds splits g, g + 16, ... in four interleaved partial sums), then
-// combines the groups by a fixed tree.
-constexpr int WR_G = 16;
-static __global__ __launch_bounds__(64 * WR_G) void k_wreduce(const float *partial, int splits, int E, int Kw, float *dW,
-                                                            float *db) {
+// Fixed-order sums of split partials, several weight gradients per launch.
+// Job j: partials [splits][E] (E = rows (Kw + 1), a multiple of 4; column Kw
+// of each row is that row's bias sum) into dW [rows][Kw] and db.  Cb = rows:
+// db[m] is row m's bias.  Cb < rows (the up-sampling, rows d Cout + co): db[c]
+// sums the bias columns of rows c, c + Cb, ...
+// A weight block has 16 waves; a job with G split groups (G = 2^gsh, about
+// splits / 16, at most 16) gives each lane a float4 of partials and each run
+// of G waves 256 consecutive elements: group g adds splits g, g + G, ... in
+// four interleaved partial sums, then the groups combine by a fixed tree (so
+// a lane adds at most 16 loads but for the 512 splits of the padded input's
+// layer, whatever the split count).  A bias block of a
+// Cb < rows job gives one bias to each of its 16 waves: lane l adds the terms
+// l, l + 64, ... of (split, row) in split-major order, then a fixed shuffle
+// tree, lane 0's sum being the result.
+constexpr int WR_G = 16, WJ_MAX = 24;
+struct WJob {
+  const float *partial;
+  float *dW, *db;
+  int splits, E, Kw, Cb;
+  int blk0, nbw;  // first block; weight blocks (then ceil(Cb / 16) bias blocks if Cb < rows)
+  int gsh;        // log2 of the split groups
+};
+struct WJobs {
+  int n;
+  WJob j[WJ_MAX];
+};
+
+static __global__ __launch_bounds__(64 * WR_G) void k_wreduce(WJobs J) {
   __shared__ float4 sh[WR_G][64];
+  int jj = 0;
+  while (jj + 1 < J.n && (int)blockIdx.x >= J.j[jj + 1].blk0) ++jj;
+  const WJob &jb = J.j[jj];
+  const int blk = (int)blockIdx.x - jb.blk0;
   const int lane = threadIdx.x & 63, gr = threadIdx.x >> 6;
-  const int e4 = blockIdx.x * 64 + lane, E4 = E / 4;
+  const int rows = jb.E / (jb.Kw + 1);
+  if (blk >= jb.nbw) {  // bias block
+    const int c = (blk - jb.nbw) * WR_G + gr, R = rows / jb.Cb, T = jb.splits * R;
+    if (c >= jb.Cb) return;
+    float s = 0.f;
+    for (int t = lane; t < T; t += 64) {
+      const int z = t / R, k = t - z * R;
+      s += jb.partial[(size_t)z * jb.E + (size_t)(c + k * jb.Cb) * (jb.Kw + 1) + jb.Kw];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) jb.db[c] = s;
+    return;
+  }
+  const int G = 1 << jb.gsh, g = gr & (G - 1);
+  const int e4 = (blk * (WR_G >> jb.gsh) + (gr >> jb.gsh)) * 64 + lane, E4 = jb.E / 4, splits = jb.splits;
   float4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
   if (e4 < E4) {
-    const float4 *p = reinterpret_cast<const float4 *>(partial) + e4;
+    const float4 *p = reinterpret_cast<const float4 *>(jb.partial) + e4;
     const size_t st = (size_t)E4;
-    int z = gr;
-    for (; z + 3 * WR_G < splits; z += 4 * WR_G) {
-      const float4 v0 = p[z * st], v1 = p[(z + WR_G) * st], v2 = p[(z + 2 * WR_G) * st], v3 = p[(z + 3 * WR_G) * st];
+    int z = g;
+    for (; z + 3 * G < splits; z += 4 * G) {
+      const float4 v0 = p[z * st], v1 = p[(z + G) * st], v2 = p[(z + 2 * G) * st], v3 = p[(z + 3 * G) * st];
       a0.x += v0.x; a0.y += v0.y; a0.z += v0.z; a0.w += v0.w;
       a1.x += v1.x; a1.y += v1.y; a1.z += v1.z; a1.w += v1.w;
       a2.x += v2.x; a2.y += v2.y; a2.z += v2.z; a2.w += v2.w;
       a3.x += v3.x; a3.y += v3.y; a3.z += v3.z; a3.w += v3.w;
     }
-    for (; z < splits; z += WR_G) {
+    for (; z < splits; z += G) {
       const float4 v = p[z * st];
       a0.x += v.x; a0.y += v.y; a0.z += v.z; a0.w += v.w;
     }
@@ -623,22 +661,22 @@ static __global__ __launch_bounds__(64 * WR_G) void k_wreduce(const float *parti
   s.w = (a0.w + a1.w) + (a2.w + a3.w);
   sh[gr][lane] = s;
   __syncthreads();
-  for (int w = WR_G / 2; w >= 1; w >>= 1) {
-    if (gr < w) {
+  for (int w = G / 2; w >= 1; w >>= 1) {
+    if (g < w) {
       float4 &d = sh[gr][lane];
       const float4 o = sh[gr + w][lane];
       d.x += o.x; d.y += o.y; d.z += o.z; d.w += o.w;
     }
     __syncthreads();
   }
-  if (gr == 0 && e4 < E4) {
-    const float4 v = sh[0][lane];
+  if (g == 0 && e4 < E4) {
+    const float4 v = sh[gr][lane];
     const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int e = 4 * e4 + k, m = e / (Kw + 1), c = e - m * (Kw + 1);
-      if (c < Kw) dW[(size_t)m * Kw + c] = vv[k];
-      else db[m] = vv[k];
+      const int e = 4 * e4 + k, m = e / (jb.Kw + 1), c = e - m * (jb.Kw + 1);
+      if (c < jb.Kw) jb.dW[(size_t)m * jb.Kw + c] = vv[k];
+      else if (jb.Cb == rows) jb.db[m] = vv[k];
     }
   }
 }
@@ -707,15 +745,6 @@ __global__ __launch_bounds__(256) void k_upfwd(DUp P) {
     const size_t q = ((size_t)b * 2 * H + Y) * 2 * W + 2 * (x0 + px) + dx;
     *reinterpret_cast<bf16x8 *>(P.out.p + q * P.out.cs + P.out.coff + c8) =
         *reinterpret_cast<const bf16x8 *>(&O[px * OPU + c8]);
-  }
-}
-
-// db[c] = sum over m = c, c + Cb, ... < M of rows[m], in ascending m.
-static __global__ __launch_bounds__(256) void k_bias_fold(const float *rows, int M, int Cb, float *db) {
-  for (int c = threadIdx.x; c < Cb; c += 256) {
-    float s = 0.f;
-    for (int m = c; m < M; m += Cb) s += rows[m];
-    db[c] = s;
   }
 }
 

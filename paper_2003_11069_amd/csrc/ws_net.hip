@@ -92,10 +92,13 @@ struct ws_net {
   Buf<float> y;                  // head output, 8 channels
   std::vector<Buf<bf16>> dpool, dmid_e, dcat, dmid_d, ddec;  // activation gradients (BF16)
   Buf<bf16> dbott, dy;
-  float *scratch = nullptr;  // split-K partials
-  float *bias_rows = nullptr;  // per-row bias sums of an up-sampling weight gradient
+  // split partials of every weight gradient of a backward pass, each layer
+  // in its own range, summed by one k_wreduce launch per WJ_MAX layers at
+  // the end of the pass
+  float *scratch = nullptr;
+  size_t scratch_floats = 0, scratch_used = 0;
+  std::vector<WJob> jobs;
   bf16 *dpre = nullptr;        // BF16 backward operand of a layer, data gradient -> weight gradient
-  size_t scratch_floats = 0;
   double *loss_part = nullptr, *loss = nullptr;
   int n_loss_blocks = 0;
   std::vector<void *> allocs;
@@ -341,20 +344,55 @@ struct WShape {
 };
 WShape wshape(int Cout, int Kw1) { return Cout < 64 ? WShape{true, Kw1, Cout} : WShape{false, Cout, Kw1}; }
 
-// Sums split partials [splits][M][Kw+1] into dW [M][Kw] and the bias column
-// into db: directly when each row is one bias (Cb = M), else through bias_rows
-// folded as db[c] = sum over rows m = c (mod Cb) in ascending m.
-void launch_split_reduce(ws_net *n, int splits, int M, int Kw, float *dW, float *db, int Cb) {
-  const int64_t E = (int64_t)M * (Kw + 1);
-  float *rows = Cb == M ? db : n->bias_rows;
-  hipLaunchKernelGGL(k_wreduce, dim3((unsigned)((E / 4 + 63) / 64)), dim3(64 * WR_G), 0, n->stream, n->scratch,
-                     splits, (int)E, Kw, dW, rows);
-  if (Cb != M) hipLaunchKernelGGL(k_bias_fold, dim3(1), dim3(256), 0, n->stream, (const float *)n->bias_rows, M, Cb, db);
+// The next range of split partials, splits x M (Kw + 1) floats (a multiple
+// of 4), or nullptr when the scratch sized at creation cannot hold it.
+float *take_partials(ws_net *n, int splits, int M, int Kw) {
+  const size_t count = (size_t)splits * M * (Kw + 1);
+  if (n->scratch_used + count > n->scratch_floats) return nullptr;
+  float *p = n->scratch + n->scratch_used;
+  n->scratch_used += count;
+  return p;
+}
+
+// Queues the sum of partials [splits][M][Kw+1] into dW [M][Kw] and the bias
+// column into db: row m's bias when Cb = M, else db[c] = sum over rows
+// m = c (mod Cb).
+void queue_split_reduce(ws_net *n, const float *partial, int splits, int M, int Kw, float *dW, float *db, int Cb) {
+  WJob j{};
+  j.partial = partial;
+  j.dW = dW;
+  j.db = db;
+  j.splits = splits;
+  j.E = M * (Kw + 1);
+  j.Kw = Kw;
+  j.Cb = Cb;
+  n->jobs.push_back(j);
+}
+
+// Launches the queued sums, WJ_MAX layers per launch, and frees the scratch.
+void flush_split_reduce(ws_net *n) {
+  for (size_t i = 0; i < n->jobs.size(); i += WJ_MAX) {
+    WJobs J{};
+    int blk = 0;
+    for (size_t k = i; k < n->jobs.size() && k < i + WJ_MAX; ++k) {
+      WJob j = n->jobs[k];
+      j.blk0 = blk;
+      j.gsh = 0;
+      while (j.gsh < 4 && (16 << j.gsh) < j.splits) ++j.gsh;  // at most 16 splits per group, or 16 groups
+      j.nbw = (j.E / 4 + (64 * WR_G >> j.gsh) - 1) / (64 * WR_G >> j.gsh);
+      const int rows = j.E / (j.Kw + 1);
+      blk += j.nbw + (j.Cb < rows ? (j.Cb + WR_G - 1) / WR_G : 0);
+      J.j[J.n++] = j;
+    }
+    hipLaunchKernelGGL(k_wreduce, dim3((unsigned)blk), dim3(64 * WR_G), 0, n->stream, J);
+  }
+  n->jobs.clear();
+  n->scratch_used = 0;
 }
 
 template <int KS, bool RELU, bool TR>
 void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act,
-                     View<const bf16> dout, int chunk, int splits, const WShape &ws) {
+                     View<const bf16> dout, int chunk, int splits, const WShape &ws, float *partial) {
   ConvBwdWeight<KS, RELU, TR> pw;
   pw.g = g;
   pw.dout = dout;
@@ -364,7 +402,7 @@ void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<
   pw.Cout = c.Cout;
   pw.dCin = Div::make(c.Cin);
   pw.chunk = chunk;
-  pw.partial = n->scratch;
+  pw.partial = partial;
   gemm(n, pw, ws.M, ws.N, splits, pick_tile_split(ws.M, ws.N));
 }
 
@@ -414,12 +452,11 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     pw.in = in;
     pw.Cin = c.Cin;
     pw.Cout = c.Cout;
-    pw.partial = n->scratch;
     pw.dpre = dpre;
     int splits;
     direct_wplan(pw.T.n, c.Cin, c.Cout, splits, pw.tps);
-    const int64_t E = (int64_t)c.Cout * (Kw + 1);
-    if ((size_t)splits * E > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+    pw.partial = take_partials(n, splits, c.Cout, Kw);
+    if (!pw.partial) return fail(WS_EINVAL, "split scratch too small");
     const int hw = direct_whw(c.Cin);
     const dim3 grid((unsigned)splits, (unsigned)(c.Cout / 32), (unsigned)std::max(1, c.Cin / (16 * hw)));
     if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1, false>), grid, dim3(128), 0, n->stream, pw);
@@ -427,15 +464,16 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2, false>), grid, dim3(256), 0, n->stream, pw);
     else if (dpre) hipLaunchKernelGGL((k_dwgrad<false, 4, true>), grid, dim3(512), 0, n->stream, pw);
     else hipLaunchKernelGGL((k_dwgrad<false, 4, false>), grid, dim3(512), 0, n->stream, pw);
-    launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
+    queue_split_reduce(n, pw.partial, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   } else {
     const WShape ws = wshape(c.Cout, Kw + 1);
     int splits, chunk;
     split_plan(P, ws.M, ws.N, splits, chunk);
-    if ((size_t)splits * c.Cout * (Kw + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
-    if (ws.tr) conv_bwd_weight<KS, RELU, true>(n, c, g, in, act, dout, chunk, splits, ws);
-    else conv_bwd_weight<KS, RELU, false>(n, c, g, in, act, dout, chunk, splits, ws);
-    launch_split_reduce(n, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
+    float *part = take_partials(n, splits, c.Cout, Kw);
+    if (!part) return fail(WS_EINVAL, "split scratch too small");
+    if (ws.tr) conv_bwd_weight<KS, RELU, true>(n, c, g, in, act, dout, chunk, splits, ws, part);
+    else conv_bwd_weight<KS, RELU, false>(n, c, g, in, act, dout, chunk, splits, ws, part);
+    queue_split_reduce(n, part, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   }
   return WS_OK;
 }
@@ -504,29 +542,29 @@ int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const bf16
     pw.in = in;
     pw.Cin = u.Cin;
     pw.Cout = u.Cout;
-    pw.partial = n->scratch;
     int hw, splits;
     up_wplan(gin, u, hw, splits, pw.ipb);
-    if ((size_t)splits * 4 * u.Cout * (u.Cin + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
+    pw.partial = take_partials(n, splits, 4 * u.Cout, u.Cin);
+    if (!pw.partial) return fail(WS_EINVAL, "split scratch too small");
     const dim3 grid((unsigned)splits, (unsigned)(4 * u.Cout / 32), (unsigned)(u.Cin / (16 * hw)));
     if (hw == 4) hipLaunchKernelGGL(k_upwgrad<4>, grid, dim3(512), 0, n->stream, pw);
     else hipLaunchKernelGGL(k_upwgrad<2>, grid, dim3(256), 0, n->stream, pw);
-    launch_split_reduce(n, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
+    queue_split_reduce(n, pw.partial, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
   } else {
-  int splits, chunk;
-  split_plan(P, 4 * u.Cout, u.Cin + 1, splits, chunk);
-  if ((size_t)splits * 4 * u.Cout * (u.Cin + 1) > n->scratch_floats) return fail(WS_EINVAL, "split scratch too small");
-  UpBwdWeight pw;
-  pw.g = gin;
-  pw.dout = dout;
-  pw.in = in;
-  pw.Cin = u.Cin;
-  pw.Cout = u.Cout;
-  pw.chunk = chunk;
-  pw.partial = n->scratch;
-  pw.dCout = Div::make(u.Cout);
-  gemm(n, pw, 4 * u.Cout, u.Cin + 1, splits, pick_tile_split(4 * u.Cout, u.Cin + 1));
-  launch_split_reduce(n, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
+    int splits, chunk;
+    split_plan(P, 4 * u.Cout, u.Cin + 1, splits, chunk);
+    UpBwdWeight pw;
+    pw.g = gin;
+    pw.dout = dout;
+    pw.in = in;
+    pw.Cin = u.Cin;
+    pw.Cout = u.Cout;
+    pw.chunk = chunk;
+    pw.partial = take_partials(n, splits, 4 * u.Cout, u.Cin);
+    if (!pw.partial) return fail(WS_EINVAL, "split scratch too small");
+    pw.dCout = Div::make(u.Cout);
+    gemm(n, pw, 4 * u.Cout, u.Cin + 1, splits, pick_tile_split(4 * u.Cout, u.Cin + 1));
+    queue_split_reduce(n, pw.partial, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
   }
   UpBwdData pd;
   pd.g = gin;
@@ -583,6 +621,8 @@ int forward(ws_net *n, const float *x, int B) {
 
 int backward(ws_net *n, int B) {
   const int L = n->L;
+  n->jobs.clear();
+  n->scratch_used = 0;
   Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
   int rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), View<const bf16>{nullptr, 0, 0}, cv(n->dy),
                                 mv(n->ddec[0]));
@@ -617,6 +657,7 @@ int backward(ws_net *n, int B) {
                          cv(n->dpool[l]), mv(n->dcat[l - 1], Cp));
     }
   }
+  flush_split_reduce(n);
   HTRY(hipGetLastError());
   return WS_OK;
 }
@@ -718,23 +759,27 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   if (!rc) rc = buf(n, n->dbott, L - 1, chans(n, L - 1));
   if (!rc) rc = buf(n, n->y, 0, 8);
   if (!rc) rc = buf(n, n->dy, 0, 8);
-  // split-K scratch: at most 1024/tiles splits of a weight-gradient matrix
+  // split partials of all weight gradients of one backward pass (each layer
+  // keeps its own range until the pass ends); per layer the larger of the
+  // implicit-GEMM and the direct plan, the most over batch sizes
   size_t worst = 0;
   for (int B = 1; B <= c->max_batch; ++B) {  // splits depend on the batch
-    auto need = [&](int l, int M, int N) {
+    size_t total = 0;
+    auto gemm_need = [&](int l, int M, int N) {
       int splits, chunk;
       split_plan(B * imgH(n, l) * imgW(n, l), M, N, splits, chunk);
-      worst = std::max(worst, (size_t)splits * M * N);
+      return (size_t)splits * M * N;
     };
     auto conv = [&](int lv, const Conv &cv) {
       const WShape w = wshape(cv.Cout, cv.KS * cv.KS * cv.Cin + 1);
-      need(lv, w.M, w.N);
+      size_t need = gemm_need(lv, w.M, w.N);
       const Img g = Img::make(B, imgH(n, lv), imgW(n, lv));
       if (cv.KS == 3 && cv.relu && direct_ok(n, g, cv.Cin, cv.Cout, true)) {
         int splits, tps;
         direct_wplan(DTiles::make(B, g.H, g.W).n, cv.Cin, cv.Cout, splits, tps);
-        worst = std::max(worst, (size_t)splits * cv.Cout * (cv.KS * cv.KS * cv.Cin + 1));
+        need = std::max(need, (size_t)splits * cv.Cout * (cv.KS * cv.KS * cv.Cin + 1));
       }
+      total += need;
     };
     for (int l = 0; l < L; ++l) {
       conv(l, n->e1[l]);
@@ -742,20 +787,22 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
       if (l < L - 1) {
         conv(l, n->d1[l]);
         conv(l, n->d2[l]);
-        need(l + 1, 4 * n->up[l].Cout, n->up[l].Cin + 1);  // over the input (coarser) pixels
+        const Up &u = n->up[l];
+        size_t need = gemm_need(l + 1, 4 * u.Cout, u.Cin + 1);  // over the input (coarser) pixels
         const Img gu = Img::make(B, imgH(n, l + 1), imgW(n, l + 1));
-        if (up_direct_wgrad(n, gu, n->up[l])) {
+        if (up_direct_wgrad(n, gu, u)) {
           int hw, splits, ipb;
-          up_wplan(gu, n->up[l], hw, splits, ipb);
-          worst = std::max(worst, (size_t)splits * 4 * n->up[l].Cout * (n->up[l].Cin + 1));
+          up_wplan(gu, u, hw, splits, ipb);
+          need = std::max(need, (size_t)splits * 4 * u.Cout * (u.Cin + 1));
         }
+        total += need;
       }
     }
     conv(0, n->head);
+    worst = std::max(worst, total);
   }
   n->scratch_floats = worst;
   if (!rc) rc = dalloc(n, &n->scratch, worst);
-  if (!rc) rc = dalloc(n, &n->bias_rows, (size_t)4 * chans(n, L - 1));
   // the largest direct layer's output gradient: C_l channels on H W / 4^l pixels
   if (!rc) rc = dalloc(n, &n->dpre, c->conv_algo == 0 ? (size_t)c->max_batch * c->H * c->W * c->base : 1);
   n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W);  // k_mse: a pixel per thread
