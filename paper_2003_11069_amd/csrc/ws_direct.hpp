@@ -28,6 +28,8 @@
 //   k_upfwd      2x2 stride-2 transposed convolution, forward;
 //   k_upwgrad    its weight and bias gradient, staged transposed like
 //                k_dwgrad, partial sums [split][4 Cout][Cin + 1].
+//   k_head       the 1x1 head, the loss and the head's gradients, for
+//                training, in one pass.
 //
 // Lane layout of the MFMA (as in ws_kernels.hpp): lane l holds
 // A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16] and receives
@@ -746,6 +748,143 @@ __global__ __launch_bounds__(256) void k_upfwd(DUp P) {
     *reinterpret_cast<bf16x8 *>(P.out.p + q * P.out.cs + P.out.coff + c8) =
         *reinterpret_cast<const bf16x8 *>(&O[px * OPU + c8]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Training head: the 1x1 head (C0 -> 8 channels, the first cout real), the
+// loss and the head's backward in one pass over the last decoder output:
+//   y[p][o]    = b[o] + sum_c W[o][c] act[p][c]             (FP32, o < cout)
+//   loss       = sum over p and o < cout of (y - t)^2         (FP64)
+//   dy[p][o]   = BF16(2 (y - t) / (P cout)), 0 for o >= cout
+//   dact[p][c] = BF16(sum_o W[o][c] dy[p][o])
+//   dW[o][c]   = sum_p dy[p][o] act[p][c],  db[o] = sum_p dy[p][o]
+// The products are those of the implicit-GEMM head (BF16 weights and
+// activations, FP32 sums); only the summation order differs.  A block takes
+// runs of 256 pixels, a pixel per thread for y, the loss, dy and dact; dW and
+// db go through the MFMA: the run's dy^T (16 rows, 8..15 zero) and act^T
+// (channels padded to 16 NT) are staged in LDS, pixels contiguous, and wave w
+// adds K steps 2w and 2w + 1 of every run.  At the end the four waves' sums
+// are added in order; the block writes partials [block][8][C0 + 1] (bias
+// last) and the FP64 loss sum of its pixels.
+struct DHead {
+  int P, C0, cout, rpb;    // pixels, head input channels, real outputs, runs per block
+  View<const bf16> act;    // last decoder output (C0 channels)
+  const bf16 *W;           // [8][C0]
+  const float *bias;       // [8]
+  const float *t;          // target [P][cout]
+  float Pc;                // P cout
+  View<bf16> dact;         // gradient of act
+  float *partial;          // [blocks][8][C0 + 1]
+  double *loss;            // [blocks]
+};
+constexpr int HD_P = 256 + 8;  // LDS pitch (bf16) of a staged row of 256 pixels
+
+inline size_t head_lds_bytes(int C0, int NT) { return (size_t)8 * C0 * 4 + (size_t)16 * HD_P * 2 + (size_t)16 * NT * HD_P * 2; }
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_head(DHead P) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char hsm[];
+  __shared__ double lsh[256];
+  const int C0 = P.C0, C8 = C0 / 8, NP = 16 * NT + 1;
+  float *Wf = reinterpret_cast<float *>(hsm);         // [8][C0]
+  bf16 *dyT = reinterpret_cast<bf16 *>(Wf + 8 * C0);  // [16][HD_P]
+  bf16 *acT = dyT + 16 * HD_P;                        // [16 NT][HD_P]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  for (int i = tid; i < 8 * C0; i += 256) Wf[i] = (float)P.W[i];
+  for (int i = tid; i < 8 * HD_P; i += 256) dyT[8 * HD_P + i] = (bf16)0.f;
+  for (int i = tid; i < (16 * NT - C0) * HD_P; i += 256) acT[C0 * HD_P + i] = (bf16)0.f;
+  float bias[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) bias[o] = P.bias[o];
+  f4 acc[NT], accb = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
+  double esum = 0.0;
+  const int nruns = (P.P + 255) / 256, r0 = blockIdx.x * P.rpb, r1 = min(nruns, r0 + P.rpb);
+  __syncthreads();
+  for (int r = r0; r < r1; ++r) {
+    const int p = r * 256 + tid;
+    const bool live = p < P.P;
+    float y[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) y[o] = bias[o];
+    const bf16 *ap = P.act.p + (size_t)p * P.act.cs + P.act.coff;
+    for (int k = 0; k < C8; ++k) {
+      const bf16x8 v = live ? *reinterpret_cast<const bf16x8 *>(ap + 8 * k) : zero8();
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float a = (float)v[j];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) y[o] += Wf[o * C0 + 8 * k + j] * a;
+        acT[(8 * k + j) * HD_P + tid] = v[j];
+      }
+    }
+    float dy[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      dy[o] = 0.f;
+      if (live && o < P.cout) {
+        const float d = y[o] - P.t[(size_t)p * P.cout + o];
+        esum += (double)d * d;
+        dy[o] = (float)(bf16)(2.f * d / P.Pc);
+      }
+      dyT[o * HD_P + tid] = (bf16)dy[o];
+    }
+    if (live) {
+      bf16 *dp = P.dact.p + (size_t)p * P.dact.cs + P.dact.coff;
+      for (int k = 0; k < C8; ++k) {
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float s = 0.f;
+#pragma unroll
+          for (int o = 0; o < 8; ++o) s += Wf[o * C0 + 8 * k + j] * dy[o];
+          v[j] = (bf16)s;
+        }
+        *reinterpret_cast<bf16x8 *>(dp + 8 * k) = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 2 * w; ks < 2 * w + 2; ++ks) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&dyT[l16 * HD_P + 32 * ks + 8 * g]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&acT[(16 * nt + l16) * HD_P + 32 * ks + 8 * g]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+      }
+      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, accb, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // the four waves' sums, rows o = 4 g + q < 8, in the staging area
+  float *red = reinterpret_cast<float *>(acT);  // [4][8][16 NT + 1]
+  if (g < 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = 4 * g + q;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) red[(w * 8 + o) * NP + 16 * nt + l16] = acc[nt][q];
+      if (l16 == 0) red[(w * 8 + o) * NP + 16 * NT] = accb[q];
+    }
+  }
+  lsh[tid] = esum;
+  __syncthreads();
+  for (int i = tid; i < 8 * (C0 + 1); i += 256) {
+    const int o = i / (C0 + 1), c = i - o * (C0 + 1), cc = c == C0 ? 16 * NT : c;
+    float s = 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s += red[(v * 8 + o) * NP + cc];
+    P.partial[(size_t)blockIdx.x * 8 * (C0 + 1) + i] = s;
+  }
+  for (int s = 128; s >= 1; s >>= 1) {
+    if (tid < s) lsh[tid] += lsh[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) P.loss[blockIdx.x] = lsh[0];
 }
 
 }  // namespace wsk

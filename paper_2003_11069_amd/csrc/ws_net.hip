@@ -583,7 +583,26 @@ View<const T> cv(const Buf<T> &b, int coff = 0) { return View<const T>{b.p, b.cs
 template <typename T>
 View<T> mv(Buf<T> &b, int coff = 0) { return View<T>{b.p, b.cs, coff}; }
 
-int forward(ws_net *n, const float *x, int B) {
+// The fused training head (k_head) serves conv_algo 0 with at most 256 head
+// input channels; else the head, loss and head gradients are separate kernels.
+bool head_fused(const ws_net *n) { return n->cfg.conv_algo == 0 && n->C0 <= 256; }
+int head_nt(int C0) {
+  int nt = 1;
+  while (16 * nt < C0) nt *= 2;
+  return nt;
+}
+// Runs of 256 pixels over at most 1024 blocks (4 waves per SIMD; 256 and 512
+// blocks measured 45 and 33 us against 30 at 3x128x256, batch 16; 2048
+// slowed the split sum of the 2048 partials).
+void head_plan(int P, int &grid, int &rpb) {
+  const int runs = (P + 255) / 256;
+  grid = std::min(1024, runs);
+  rpb = (runs + grid - 1) / grid;
+  grid = (runs + rpb - 1) / rpb;
+}
+
+// head = false: stops before the head (the training head computes it)
+int forward(ws_net *n, const float *x, int B, bool head = true) {
   const int L = n->L;
   const int P0 = B * n->cfg.H * n->cfg.W;
   hipLaunchKernelGGL(k_pack_input, dim3(blocks(P0)), dim3(256), 0, n->stream, x, P0, n->cfg.cin, n->xin.p);
@@ -612,21 +631,64 @@ int forward(ws_net *n, const float *x, int B) {
     rc = conv_fwd(n, n->d2[l], gl, cv(n->mid_d[l]), mv(n->dec[l]));
     if (rc) return rc;
   }
-  Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
-  int rc = conv_fwd_t<1, false, true>(n, n->head, g0, cv(n->dec[0]), View<bf16>{nullptr, 0, 0}, mv(n->y));
-  if (rc) return rc;
+  if (head) {
+    Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
+    int rc = conv_fwd_t<1, false, true>(n, n->head, g0, cv(n->dec[0]), View<bf16>{nullptr, 0, 0}, mv(n->y));
+    if (rc) return rc;
+  }
   HTRY(hipGetLastError());
   return WS_OK;
 }
 
-int backward(ws_net *n, int B) {
+// Loss (into n->loss) and all gradients, after forward(n, x, B, !head_fused(n)).
+int backward(ws_net *n, const float *target, int B) {
   const int L = n->L;
   n->jobs.clear();
   n->scratch_used = 0;
   Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
-  int rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), View<const bf16>{nullptr, 0, 0}, cv(n->dy),
-                                mv(n->ddec[0]));
-  if (rc) return rc;
+  const int P = B * n->cfg.H * n->cfg.W;
+  int rc = WS_OK, nlb;
+  if (head_fused(n)) {
+    DHead h{};
+    h.P = P;
+    h.C0 = n->C0;
+    h.cout = n->cfg.cout;
+    h.act = cv(n->dec[0]);
+    h.W = n->head.Wt;
+    h.bias = n->params + n->head.b_off;
+    h.t = target;
+    h.Pc = (float)((double)P * n->cfg.cout);
+    h.dact = mv(n->ddec[0]);
+    h.loss = n->loss_part;
+    int grid;
+    head_plan(P, grid, h.rpb);
+    h.partial = take_partials(n, grid, 8, n->C0);
+    if (!h.partial) return fail(WS_EINVAL, "split scratch too small");
+    const int nt = head_nt(n->C0);
+    const size_t lds = head_lds_bytes(n->C0, nt);
+    switch (nt) {
+#define WS_HEAD(NT)                                                                                   \
+  case NT:                                                                                            \
+    HTRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_head<NT>),                             \
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                  \
+    hipLaunchKernelGGL(k_head<NT>, dim3(grid), dim3(256), lds, n->stream, h);                         \
+    break;
+      WS_HEAD(1) WS_HEAD(2) WS_HEAD(4) WS_HEAD(8) WS_HEAD(16)
+#undef WS_HEAD
+      default: return fail(WS_EINVAL, "head input channels beyond 256");
+    }
+    queue_split_reduce(n, h.partial, grid, 8, n->C0, n->grads + n->head.w_off, n->grads + n->head.b_off, 8);
+    nlb = grid;
+  } else {
+    nlb = (int)blocks(P);
+    hipLaunchKernelGGL(k_mse, dim3(nlb), dim3(256), 0, n->stream, n->y.p, target, P, n->cfg.cout, n->dy.p,
+                       n->loss_part);
+    rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), View<const bf16>{nullptr, 0, 0}, cv(n->dy),
+                              mv(n->ddec[0]));
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, n->stream, n->loss_part, nlb,
+                     1.0 / ((double)P * n->cfg.cout), n->loss);
   for (int l = 0; l <= L - 2; ++l) {
     Img gl = Img::make(B, imgH(n, l), imgW(n, l)), gu = Img::make(B, imgH(n, l + 1), imgW(n, l + 1));
     rc = conv_bwd_t<3, true>(n, n->d2[l], gl, cv(n->mid_d[l]), cv(n->dec[l]), cv(n->ddec[l]), mv(n->dmid_d[l]));
@@ -799,6 +861,11 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
       }
     }
     conv(0, n->head);
+    {
+      int grid, rpb;
+      head_plan(B * c->H * c->W, grid, rpb);
+      total += (size_t)grid * 8 * (n->C0 + 1);  // the training head's partials
+    }
     worst = std::max(worst, total);
   }
   n->scratch_floats = worst;
@@ -875,15 +942,9 @@ int ws_backward(ws_net *n, const float *x, const float *target, int32_t batch, d
   if (!n || !x || !target) return fail(WS_EINVAL, "NULL argument");
   int rc = check_batch(n, batch);
   if (rc) return rc;
-  rc = forward(n, x, batch);
+  rc = forward(n, x, batch, !head_fused(n));
   if (rc) return rc;
-  const int P = batch * n->cfg.H * n->cfg.W;
-  const int nb = (int)blocks(P);
-  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, n->stream, n->y.p, target, P, n->cfg.cout, n->dy.p,
-                     n->loss_part);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, n->stream, n->loss_part, nb,
-                     1.0 / ((double)P * n->cfg.cout), n->loss);
-  rc = backward(n, batch);
+  rc = backward(n, target, batch);
   if (rc) return rc;
   if (loss) {
     HTRY(hipMemcpyAsync(loss, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));

@@ -81,6 +81,10 @@ CASES = [
     # (level 2 of the second, 8 x 16, falls back to the implicit GEMM)
     (2, 32, 16, 64, 2),
     (3, 32, 32, 64, 2),
+    # wide heads: the training head with 64 and 136 input channels (channel
+    # tiles padded to 64 and 256; the latter needs more than 64 KB of LDS)
+    (2, 64, 16, 32, 2),
+    (2, 136, 16, 32, 1),
 ]
 
 
@@ -185,7 +189,7 @@ def test_training_reduces_loss():
 
 
 EXACT = [(2, 8, 16, 32, 2, 4), (3, 24, 32, 32, 2, 2), (2, 32, 16, 64, 2, 4), (3, 32, 32, 64, 1, 2),
-         (4, 32, 128, 256, 1, 2)]
+         (4, 32, 128, 256, 1, 2), (2, 64, 16, 32, 2, 4)]
 
 
 @pytest.mark.parametrize("L,base,H,W,B,cout", EXACT)
