@@ -10,9 +10,9 @@
 // backward operand once per tap).
 //
 //   k_dconv      forward (BF16 input; bias, ReLU, BF16 output) and
-//                backward-data (BF16 output gradient times the ReLU mask
-//                while staging; BF16 output; optionally that masked operand
-//                too, for the weight gradient).  The staged operand
+//                backward-data (the layer's output gradient, stored already
+//                masked by its ReLU; BF16 output, masked by the ReLU of the
+//                input's producer).  The staged operand
 //                has Kc channels (a multiple of 32, or the 8 of the padded
 //                network input), the output Nc (a multiple of 32).  Weights
 //                [Nc][9][Kc]: the forward W, or for backward-data its
@@ -73,17 +73,15 @@ struct DConv {
   DTiles T;
   int tpb;               // tiles per block (block b runs tiles b tpb ..)
   View<const bf16> x;    // forward: input activations (Kc channels)
-  View<const bf16> dx;   // backward-data: output gradient of the layer (Kc channels)
-  View<const bf16> act;  // backward-data: the layer's output (ReLU mask)
+  View<const bf16> dx;   // backward-data: output gradient of the layer (Kc
+                         // channels), already masked by the layer's ReLU
   int Kc, Nc;
   const bf16 *Wk;        // [Nc][9][Kc]
   const float *bias;     // forward
   View<bf16> y;          // forward output (Nc channels)
   View<bf16> dy;         // backward-data output (stored, not added)
-  bf16 *dpre;            // backward-data: when set, the BF16 operand (output
-                         // gradient x mask) of every tile's own pixels is
-                         // also written here, [pixel][Kc], for the weight
-                         // gradient (by the blocks of the first N group)
+  View<const bf16> dmask;  // backward-data: output of the input's producer; dy
+  int mc0;                 // is zeroed where it is not positive, channels >= mc0
 };
 
 // Block: a run of tpb tiles x 32 NW output channels (blockIdx.y), 4 NW
@@ -101,8 +99,8 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
   constexpr int CPP = C8 ? 1 : 4;  // 8-channel chunks per staged pixel
   constexpr int XN = DH * DW * CPP, XIT = (XN + NTH - 1) / NTH;
   constexpr int WN = NWS * BN * 4, WIT = (WN + NTH - 1) / NTH;
-  constexpr int OP = 32 + 8;  // pixel pitch of the forward output staged through Xs (NW = 1)
-  constexpr int XS = (NW > 1 || DH * DW * XP > 4 * 64 * OP) ? DH * DW * XP : 4 * 64 * OP;
+  constexpr int OP = 32 + 8;  // pixel pitch of the output staged through Xs
+  constexpr int XS = DH * DW * XP > 4 * NW * 64 * OP ? DH * DW * XP : 4 * NW * 64 * OP;
   __shared__ __attribute__((aligned(16))) bf16 Xs[XS];
   __shared__ __attribute__((aligned(16))) bf16 Ws[NWS * BN * DP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
@@ -158,48 +156,42 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       }
     }
   };
+  const View<const bf16> &X = BWD ? P.dx : P.x;  // the staged operand
   auto gload = [&](int item) {
-    bf16x8 xg[BWD ? XIT : 1];
     const int t = t0 + item / slices, s = item % slices;
     int b, y0, x0;
     P.T.at(t, b, y0, x0);
     const int64_t tb = (int64_t)(b * H + y0) * W + x0;  // the tile's first pixel
-    const bf16 *xb = P.x.p + tb * P.x.cs + P.x.coff + s * 32;
-    const bf16 *db = P.dx.p + tb * P.dx.cs + P.dx.coff + s * 32;
-    const bf16 *ab = P.act.p + tb * P.act.cs + P.act.coff + s * 32;
+    const bf16 *xb = X.p + tb * X.cs + X.coff + s * 32;
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
       const int q = tid + NTH * it;
       const int pix = q / CPP, ch = (q - pix * CPP) * 8, rr = pix / DW;
       const int yy = y0 + rr - 1, xx = x0 + pix - rr * DW - 1;
       const bool in = q < XN && yy >= 0 && yy < H && xx >= 0 && xx < W;
-      if (BWD) {
-        xg[it] = xa[it] = zero8();
-        if (in) {
-          xg[it] = *reinterpret_cast<const bf16x8 *>(db + rel[it] * P.dx.cs + ch);
-          xa[it] = *reinterpret_cast<const bf16x8 *>(ab + rel[it] * P.act.cs + ch);
-        }
-      } else {
-        xa[it] = in ? *reinterpret_cast<const bf16x8 *>(xb + rel[it] * P.x.cs + ch) : zero8();
-      }
-    }
-    if (BWD) {  // output gradient times the ReLU mask
-#pragma unroll
-      for (int it = 0; it < XIT; ++it) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xa[it][j] = (float)xa[it][j] > 0.f ? xg[it][j] : (bf16)0.f;
-      }
-      if (P.dpre && n0 == 0) {  // the tile's own pixels, for the weight gradient
-#pragma unroll
-        for (int it = 0; it < XIT; ++it) {
-          const int q = tid + NTH * it;
-          const int pix = q / CPP, ch = (q - pix * CPP) * 8, rr = pix / DW, cc = pix - rr * DW;
-          if (q < XN && rr >= 1 && rr <= DT_H && cc >= 1 && cc <= DT_W)
-            *reinterpret_cast<bf16x8 *>(P.dpre + (size_t)(tb + rel[it]) * P.Kc + s * 32 + ch) = xa[it];
-        }
-      }
+      xa[it] = in ? *reinterpret_cast<const bf16x8 *>(xb + rel[it] * X.cs + ch) : zero8();
     }
     if (!SL1) wload(s);
+  };
+  // backward-data: the output mask of the tile's 16-byte output rows (four per
+  // lane, as the epilogue stores them), loaded before the next item's staging
+  // so that waiting for it does not wait for the prefetch
+  bf16x8 mk[BWD ? 4 : 1];
+  auto mload = [&](int item) {
+    int b, y0, x0;
+    P.T.at(t0 + item / slices, b, y0, x0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = lane + 64 * k, px = e / 4, c8 = (e - px * 4) * 8;
+      const int row = 2 * rg + px / 32, col = px % 32, c = n0 + 32 * ng + c8;
+      const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
+      if (c >= P.mc0) {
+        mk[k] = *reinterpret_cast<const bf16x8 *>(P.dmask.p + p * P.dmask.cs + P.dmask.coff + c);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) mk[k][j] = (bf16)1.f;  // not a ReLU output: kept
+      }
+    }
   };
   auto lstore = [&](int item) {
 #pragma unroll
@@ -221,6 +213,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
     if (item) __syncthreads();  // the previous item's reads are done
     lstore(item);
     __syncthreads();
+    if (BWD && P.dmask.p && item % slices == slices - 1) mload(item);
     if (item + 1 < items) gload(item + 1);
 #pragma unroll
     for (int w = 0; w < NWS; ++w) {
@@ -250,57 +243,38 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       }
     }
     if (item % slices != slices - 1) continue;
-    // the tile's last slice: bias and ReLU (forward) and store (no global
-    // loads here: they would wait for the prefetch)
+    // the tile's last slice: bias and ReLU (forward), then each wave's 64
+    // pixels x 32 channels through its own part of Xs (pixel pitch OP) as
+    // 16-byte rows, masked (backward-data) and stored; no global loads here
+    // (they would wait for the prefetch)
     int b, y0, x0;
     P.T.at(t0 + item / slices, b, y0, x0);
-    if (NW > 1) {
+    __syncthreads();  // every wave is done reading Xs for this item
+    bf16 *O = Xs + wave * 64 * OP;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 2 * rg + (i >> 1);
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const int n = nw0 + 16 * j + l16;
+      for (int j = 0; j < NT; ++j) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int col = 16 * (i & 1) + 4 * g + q;
-            const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
-            if (BWD) {
-              P.dy.p[p * P.dy.cs + P.dy.coff + n] = (bf16)acc[i][j][q];
-            } else {
-              const float r = acc[i][j][q] + bias[j];
-              P.y.p[p * P.y.cs + P.y.coff + n] = (bf16)(r > 0.f ? r : 0.f);
-            }
-          }
-          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 4; ++q) {
+          const float r = acc[i][j][q] + bias[j];
+          O[(32 * (i >> 1) + 16 * (i & 1) + 4 * g + q) * OP + 16 * j + l16] = (bf16)(BWD ? r : r > 0.f ? r : 0.f);
         }
+        acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
-    } else {
-      // BF16 results (forward: with bias and ReLU) through LDS (each wave's
-      // 64 pixels x 32 channels in its own part of Xs, pixel pitch OP), then
-      // 16-byte stores
-      __syncthreads();  // every wave is done reading Xs for this item
-      bf16 *O = Xs + wave * 64 * OP;
+    __syncthreads();
+    const View<bf16> &Y = BWD ? P.dy : P.y;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k) {
+      const int e = lane + 64 * k, px = e / 4, c8 = (e - px * 4) * 8;
+      const int row = 2 * rg + px / 32, col = px % 32;
+      const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
+      bf16x8 v = *reinterpret_cast<const bf16x8 *>(&O[px * OP + c8]);
+      if (BWD && P.dmask.p) {
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float r = acc[i][j][q] + bias[j];
-            O[(32 * (i >> 1) + 16 * (i & 1) + 4 * g + q) * OP + 16 * j + l16] = (bf16)(BWD ? r : r > 0.f ? r : 0.f);
-          }
-          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = lane + 64 * k, px = e / 4, c8 = (e - px * 4) * 8;
-        const int row = 2 * rg + px / 32, col = px % 32;
-        const size_t p = (size_t)(b * H + y0 + row) * W + x0 + col;
-        const View<bf16> &Y = BWD ? P.dy : P.y;
-        *reinterpret_cast<bf16x8 *>(Y.p + p * Y.cs + Y.coff + n0 + c8) = *reinterpret_cast<const bf16x8 *>(&O[px * OP + c8]);
+        for (int j = 0; j < 8; ++j) v[j] = (float)mk[k][j] > 0.f ? v[j] : (bf16)0.f;
       }
+      *reinterpret_cast<bf16x8 *>(Y.p + p * Y.cs + Y.coff + n0 + 32 * ng + c8) = v;
     }
   }
 }
@@ -310,12 +284,11 @@ struct DWGrad {
   Img g;
   DTiles T;
   int tps;                 // tiles per split (split z sums tiles z tps ..)
-  View<const bf16> dout;   // output gradient of the layer (Cout channels)
-  View<const bf16> act;    // the layer's output (ReLU mask)
+  View<const bf16> dout;   // output gradient of the layer (Cout channels),
+                           // already masked by the layer's ReLU
   View<const bf16> in;     // the layer's input (Cin channels)
   int Cin, Cout;
   float *partial;          // [splits][Cout][9 Cin + 1]
-  const bf16 *dpre;        // DPRE: the BF16 operand (output gradient x mask), [pixel][Cout]
 };
 
 constexpr int WA_P = DT_H * DT_W + 8;  // co pitch (bf16) of the transposed output gradient: 528 B
@@ -326,9 +299,8 @@ constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
 // padded network input, whose channels 8..15 are staged as zeros), 2 HW
 // waves.  Wave w: output channels 16 (w & 1), input channels 16 (w >> 1), all
 // nine taps; K = the 32 pixels of one tile row.  The output-gradient tile is
-// staged once for all 16 HW input channels: read as the BF16 operand the
-// data gradient left (DPRE), or as the gradient and the ReLU mask.
-template <bool C8, int HW, bool DPRE>
+// staged once for all 16 HW input channels.
+template <bool C8, int HW>
 __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   constexpr int CI = 16 * HW, NTH = 128 * HW;
   __shared__ __attribute__((aligned(16))) bf16 As[32 * WA_P];  // dPre^T [co][r][c]
@@ -345,12 +317,11 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
   const int z = blockIdx.x;
   const int tb = z * P.tps, te = min(P.T.n, tb + P.tps);
-  // staging registers of one tile: output gradient (two pixels x 8 channels
-  // per item: the gradient and the mask), input (two pixels x 8 channels)
+  // staging registers of one tile: output gradient and input, two pixels x
+  // 8 channels per item
   constexpr int AN = DT_H * DT_W / 2 * 4, AIT = AN / NTH;
   constexpr int NCH = CI / 8, BN_ = DH * (DW / 2) * NCH, BIT = (BN_ + NTH - 1) / NTH;
-  bf16x8 ga[DPRE ? 1 : AIT][2];
-  bf16x8 ma[AIT][2], ib[BIT][2];  // DPRE: ma holds the BF16 operand itself
+  bf16x8 ga[AIT][2], ib[BIT][2];
   auto gload = [&](int t) {
     int b, y0, x0;
     P.T.at(t, b, y0, x0);
@@ -362,12 +333,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const size_t o = (size_t)(p + e);
-        if constexpr (DPRE) {
-          ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.dpre + o * P.Cout + co0 + 8 * cq);
-        } else {
-          ga[it][e] = *reinterpret_cast<const bf16x8 *>(P.dout.p + o * P.dout.cs + P.dout.coff + co0 + 8 * cq);
-          ma[it][e] = *reinterpret_cast<const bf16x8 *>(P.act.p + o * P.act.cs + P.act.coff + co0 + 8 * cq);
-        }
+        ga[it][e] = *reinterpret_cast<const bf16x8 *>(P.dout.p + o * P.dout.cs + P.dout.coff + co0 + 8 * cq);
       }
     }
 #pragma unroll
@@ -388,20 +354,9 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
     for (int it = 0; it < AIT; ++it) {
       const int q = tid + NTH * it;
       const int cq = q & 3, pp = q >> 2, r = pp >> 4, c = 2 * (pp & 15);
-      bf16 v[2][8];
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        if constexpr (DPRE) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) v[e][j] = ma[it][e][j];
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) v[e][j] = (float)ma[it][e][j] > 0.f ? ga[it][e][j] : (bf16)0.f;
-        }
-      }
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * WA_P + r * DT_W + c]) = pack_bf16(v[0][j], v[1][j]);
+        *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * WA_P + r * DT_W + c]) = pack_bf16(ga[it][0][j], ga[it][1][j]);
     }
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
@@ -756,7 +711,8 @@ __global__ __launch_bounds__(256) void k_upfwd(DUp P) {
 //   y[p][o]    = b[o] + sum_c W[o][c] act[p][c]             (FP32, o < cout)
 //   loss       = sum over p and o < cout of (y - t)^2         (FP64)
 //   dy[p][o]   = BF16(2 (y - t) / (P cout)), 0 for o >= cout
-//   dact[p][c] = BF16(sum_o W[o][c] dy[p][o])
+//   dact[p][c] = BF16(sum_o W[o][c] dy[p][o]) where act[p][c] > 0, else 0
+//                (act is a ReLU output; its gradient is stored masked)
 //   dW[o][c]   = sum_p dy[p][o] act[p][c],  db[o] = sum_p dy[p][o]
 // The products are those of the implicit-GEMM head (BF16 weights and
 // activations, FP32 sums); only the summation order differs.  A block takes
@@ -812,8 +768,13 @@ __global__ __launch_bounds__(256) void k_head(DHead P) {
 #pragma unroll
     for (int o = 0; o < 8; ++o) y[o] = bias[o];
     const bf16 *ap = P.act.p + (size_t)p * P.act.cs + P.act.coff;
-    for (int k = 0; k < C8; ++k) {
+    constexpr bool KEEP = NT <= 4;  // the pixel's activations stay in registers for the mask
+    bf16x8 av[KEEP ? 2 * NT : 1];
+#pragma unroll
+    for (int k = 0; k < (KEEP ? 2 * NT : C8); ++k) {
+      if (k >= C8) break;
       const bf16x8 v = live ? *reinterpret_cast<const bf16x8 *>(ap + 8 * k) : zero8();
+      if constexpr (KEEP) av[k] = v;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const float a = (float)v[j];
@@ -835,14 +796,17 @@ __global__ __launch_bounds__(256) void k_head(DHead P) {
     }
     if (live) {
       bf16 *dp = P.dact.p + (size_t)p * P.dact.cs + P.dact.coff;
-      for (int k = 0; k < C8; ++k) {
+#pragma unroll
+      for (int k = 0; k < (KEEP ? 2 * NT : C8); ++k) {
+        if (k >= C8) break;
+        const bf16x8 a = KEEP ? av[k] : *reinterpret_cast<const bf16x8 *>(ap + 8 * k);  // the ReLU mask
         bf16x8 v;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           float s = 0.f;
 #pragma unroll
           for (int o = 0; o < 8; ++o) s += Wf[o * C0 + 8 * k + j] * dy[o];
-          v[j] = (bf16)s;
+          v[j] = (float)a[j] > 0.f ? (bf16)s : (bf16)0.f;
         }
         *reinterpret_cast<bf16x8 *>(dp + 8 * k) = v;
       }

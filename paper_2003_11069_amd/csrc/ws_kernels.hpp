@@ -15,6 +15,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace wsk {
 
@@ -116,6 +117,15 @@ __device__ __forceinline__ void put_chunk(bf16 (*S)[LD], int row, int k, const b
   }
 }
 
+// Problems with BF16 outputs in rows of 8 channels supply keep8(m, n) (the
+// output mask of such a row) and store8(m, n, v, keep): the engine stages the
+// block's results through LDS and stores 16-byte rows, all of a thread's
+// masks read before its first store (a store might alias them).
+template <class P, class = void>
+struct HasRows : std::false_type {};
+template <class P>
+struct HasRows<P, decltype((void)&P::store8)> : std::true_type {};
+
 template <class P, int BM_, int BN_, int KB = BK>
 __global__ __launch_bounds__(256) void k_gemm(P prob) {
   constexpr int WM = BM_ / 2, WN = BN_ / 2, TM = WM / 16, TN = WN / 16;
@@ -123,8 +133,9 @@ __global__ __launch_bounds__(256) void k_gemm(P prob) {
   using MA = ChunkMap<P::A_LAYOUT, BM_, KB>;
   using MB = ChunkMap<P::B_LAYOUT, BN_, KB>;
   constexpr int CA = (MA::N + 255) / 256, CB = (MB::N + 255) / 256;
-  __shared__ __attribute__((aligned(16))) bf16 As[2][BM_][LD];
-  __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN_][LD];
+  __shared__ __attribute__((aligned(16))) bf16 smem[2 * (BM_ + BN_) * LD];
+  auto As = reinterpret_cast<bf16 (*)[BM_][LD]>(smem);
+  auto Bs = reinterpret_cast<bf16 (*)[BN_][LD]>(smem + 2 * BM_ * LD);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM_, n0 = blockIdx.y * BN_;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
@@ -202,16 +213,42 @@ __global__ __launch_bounds__(256) void k_gemm(P prob) {
     __syncthreads();
     buf ^= 1;
   }
+  if constexpr (HasRows<P>::value) {
+    constexpr int OPB = BN_ + 8, R8 = BN_ / 8, NCH = BM_ * R8 / 256;  // 16-byte rows per thread
+    static_assert(BM_ * OPB <= 2 * (BM_ + BN_) * LD, "output tile exceeds the staging LDS");
+    bf16 *O = smem;
+    __syncthreads();  // the last K step's reads are done
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
-        const int n = n0 + wn + 16 * j + (lane & 15);
-        prob.store(m, n, acc[i][j][q], blockIdx.z);
-      }
+        for (int q = 0; q < 4; ++q)
+          O[(wm + 16 * i + 4 * (lane >> 4) + q) * OPB + wn + 16 * j + (lane & 15)] = (bf16)acc[i][j][q];
+    __syncthreads();
+    bf16x8 kp[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int e = tid + 256 * c, r = e / R8, c8 = (e - r * R8) * 8;
+      kp[c] = prob.keep8(m0 + r, n0 + c8);
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int e = tid + 256 * c, r = e / R8, c8 = (e - r * R8) * 8;
+      prob.store8(m0 + r, n0 + c8, *reinterpret_cast<const bf16x8 *>(&O[r * OPB + c8]), kp[c]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+          const int n = n0 + wn + 16 * j + (lane & 15);
+          prob.store(m, n, acc[i][j][q], blockIdx.z);
+        }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -254,32 +291,48 @@ struct ConvFwd {
   }
 };
 
-// Gradient operand of a layer output: dOut (BF16) times the ReLU mask of the
-// forward output (act > 0).
-template <bool RELU>
-__device__ __forceinline__ bf16x8 grad8(const View<const bf16> &d, const View<const bf16> &act, int q, int c) {
-  bf16x8 r = *reinterpret_cast<const bf16x8 *>(d.p + (size_t)q * d.cs + d.coff + c);
-  if (RELU) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(act.p + (size_t)q * act.cs + act.coff + c);
+// Eight channels of pixel q of a BF16 tensor.
+__device__ __forceinline__ bf16x8 ld8(const View<const bf16> &d, int q, int c) {
+  return *reinterpret_cast<const bf16x8 *>(d.p + (size_t)q * d.cs + d.coff + c);
+}
+
+// The gradient of a ReLU layer's output is stored as zero where the layer's
+// output (mask) is not positive, for channels c >= mc0 (channels below mc0 of
+// a concatenated buffer are not a ReLU output); no mask when mask.p is null.
+// Every activation gradient is stored this way, so the consumers (data and
+// weight gradients of that layer) read it as their operand directly.
+// row_mask: the mask of output row (pixel m, channels n .. n + 7), the
+// producer's output there, or ones where none applies (mc0 is a multiple of 8,
+// so a row is either wholly below it or not).
+__device__ __forceinline__ bf16x8 row_mask(const View<const bf16> &mask, int mc0, int P, int C, int m, int n) {
+  if (mask.p && n >= mc0 && m < P && n < C) return ld8(mask, m, n);
+  bf16x8 o;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) r[j] = (float)a[j] > 0.f ? r[j] : (bf16)0.f;
-  }
-  return r;
+  for (int j = 0; j < 8; ++j) o[j] = (bf16)1.f;
+  return o;
+}
+__device__ __forceinline__ void store_masked(const View<bf16> &d, int m, int n, bf16x8 v, bf16x8 k) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (float)k[j] > 0.f ? v[j] : (bf16)0.f;
+  *reinterpret_cast<bf16x8 *>(d.p + (size_t)m * d.cs + d.coff + n) = v;
 }
 
 // Backward-data of ConvFwd: dIn[p, ci] = sum_{ky,kx,co} WtT[ci][(ky*KS+kx)*Cout + co]
-//   dPre[p + (ky-r, kx-r), co],  WtT = weights flipped in (ky,kx) and transposed.
-// M = pixels, N = Cin, K = KS*KS*Cout (Cout multiple of 8).  Writes BF16.
-template <int KS, bool RELU>
+//   dPre[p + (ky-r, kx-r), co],  WtT = weights flipped in (ky,kx) and transposed,
+// dPre the layer's output gradient, already masked by its ReLU.  M = pixels,
+// N = Cin, K = KS*KS*Cout (Cout multiple of 8).  Writes BF16, masked by the
+// ReLU of the layer that produced the input (row_mask).
+template <int KS>
 struct ConvBwdData {
   static constexpr int A_LAYOUT = ROW, B_LAYOUT = ROW;
   Img g;
   View<const bf16> dout;
-  View<const bf16> act;  // forward output (ReLU mask)
   int Cin, Cout;
   Div dCout;
   const bf16 *WtT;  // [Cin][K]
   View<bf16> din;
+  View<const bf16> mask;  // output mask (the input's producer), channels >= mc0
+  int mc0;
   __device__ __forceinline__ int K() const { return KS * KS * Cout; }
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = K(); }
   __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
@@ -289,7 +342,7 @@ struct ConvBwdData {
     g.split(m, b, y, x);
     const int yy = y + tap / KS - KS / 2, xx = x + tap % KS - KS / 2;
     if (yy < 0 || yy >= g.H || xx < 0 || xx >= g.W) return zero8();
-    return grad8<RELU>(dout, act, (b * g.H + yy) * g.W + xx, co);
+    return ld8(dout, (b * g.H + yy) * g.W + xx, co);
   }
   __device__ __forceinline__ bf16x8 b(int n, int k, int kend, int) const {
     if (n >= Cin || k >= kend) return zero8();
@@ -299,6 +352,10 @@ struct ConvBwdData {
     if (m >= g.P() || n >= Cin) return;
     din.p[(size_t)m * din.cs + din.coff + n] = (bf16)v;
   }
+  __device__ __forceinline__ bf16x8 keep8(int m, int n) const { return row_mask(mask, mc0, g.P(), Cin, m, n); }
+  __device__ __forceinline__ void store8(int m, int n, bf16x8 v, bf16x8 k) const {
+    if (m < g.P() && n < Cin) store_masked(din, m, n, v, k);
+  }
 };
 
 // Backward-weight of ConvFwd, split over pixels:
@@ -307,12 +364,11 @@ struct ConvBwdData {
 // writes partial[z][co][k] (FP32), summed in fixed order by k_wreduce.
 // Both operands are COL chunks (8 channels of one pixel).  TR = false: M =
 // Cout, N = K + 1; TR = true (narrow Cout): M = K + 1, N = Cout.
-template <int KS, bool RELU, bool TR = false>
+template <int KS, bool TR = false>
 struct ConvBwdWeight {
   static constexpr int A_LAYOUT = COL, B_LAYOUT = COL;
   Img g;
-  View<const bf16> dout;
-  View<const bf16> act;
+  View<const bf16> dout;  // output gradient, masked by the layer's ReLU
   View<const bf16> in;
   int Cin, Cout;
   Div dCin;
@@ -324,7 +380,7 @@ struct ConvBwdWeight {
     e = min(g.P(), b + chunk);
   }
   __device__ __forceinline__ bf16x8 dpre(int co, int p, int kend) const {
-    return (p < kend && co < Cout) ? grad8<RELU>(dout, act, p, co) : zero8();
+    return (p < kend && co < Cout) ? ld8(dout, p, co) : zero8();
   }
   __device__ __forceinline__ bf16x8 col(int n, int p, int kend) const {
     bf16x8 v = zero8();
@@ -405,6 +461,7 @@ struct UpBwdData {
   Div dCout;
   const bf16 *WtT;  // [Cin][4][Cout]
   View<bf16> din;
+  View<const bf16> mask;  // the input's producer's output (ReLU mask)
   __device__ __forceinline__ void krange(int, int &b, int &e) const { b = 0; e = 4 * Cout; }
   __device__ __forceinline__ bf16x8 a(int m, int k, int kend, int) const {
     if (m >= g.P() || k >= kend) return zero8();
@@ -418,6 +475,10 @@ struct UpBwdData {
   __device__ __forceinline__ void store(int m, int n, float v, int) const {
     if (m >= g.P() || n >= Cin) return;
     din.p[(size_t)m * din.cs + din.coff + n] = (bf16)v;
+  }
+  __device__ __forceinline__ bf16x8 keep8(int m, int n) const { return row_mask(mask, 0, g.P(), Cin, m, n); }
+  __device__ __forceinline__ void store8(int m, int n, bf16x8 v, bf16x8 k) const {
+    if (m < g.P() && n < Cin) store_masked(din, m, n, v, k);
   }
 };
 
@@ -458,7 +519,8 @@ struct UpBwdWeight {
 // ---------------------------------------------------------------------------
 // 2x2 max pooling (stride 2): forward on BF16, backward routes the gradient to
 // the first maximum in the order (0,0), (0,1), (1,0), (1,1) and adds it to the
-// input gradient.  The forward handles one pooled pixel and 8 channels (C is
+// input gradient where that maximum is positive (the pooled input is a ReLU
+// output, and its stored gradient is masked).  The forward handles one pooled pixel and 8 channels (C is
 // a multiple of 8) per thread, with 16-byte vectors.
 __device__ __forceinline__ void pool_split(const Img &g, int i, int C8, int &c, int &t, int &b, int &y, int &x) {
   const int Ho = g.H / 2, Wo = g.W / 2;
@@ -513,6 +575,7 @@ static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16>
     const float v = (float)in.p[q * in.cs + in.coff + c];
     if (v > best) { best = v; arg = d; }
   }
+  if (!(best > 0.f)) return;
   const size_t q = ((size_t)b * g.H + 2 * y + (arg >> 1)) * g.W + 2 * x + (arg & 1);
   bf16 &d = din.p[q * din.cs + din.coff + c];
   d = (bf16)((float)d + (float)dout.p[(size_t)t * dout.cs + dout.coff + c]);

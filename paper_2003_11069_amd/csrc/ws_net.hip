@@ -98,7 +98,6 @@ struct ws_net {
   float *scratch = nullptr;
   size_t scratch_floats = 0, scratch_used = 0;
   std::vector<WJob> jobs;
-  bf16 *dpre = nullptr;        // BF16 backward operand of a layer, data gradient -> weight gradient
   double *loss_part = nullptr, *loss = nullptr;
   int n_loss_blocks = 0;
   std::vector<void *> allocs;
@@ -203,8 +202,8 @@ template <class P>
 struct DeepK {
   static constexpr int bm = 0, bn = 0;
 };
-template <bool RELU>
-struct DeepK<ConvBwdData<3, RELU>> {
+template <>
+struct DeepK<ConvBwdData<3>> {
   static constexpr int bm = 128, bn = 32;
 };
 template <bool RELU, bool F32>
@@ -390,13 +389,12 @@ void flush_split_reduce(ws_net *n) {
   n->scratch_used = 0;
 }
 
-template <int KS, bool RELU, bool TR>
-void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act,
-                     View<const bf16> dout, int chunk, int splits, const WShape &ws, float *partial) {
-  ConvBwdWeight<KS, RELU, TR> pw;
+template <int KS, bool TR>
+void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> dout, int chunk,
+                     int splits, const WShape &ws, float *partial) {
+  ConvBwdWeight<KS, TR> pw;
   pw.g = g;
   pw.dout = dout;
-  pw.act = act;
   pw.in = in;
   pw.Cin = c.Cin;
   pw.Cout = c.Cout;
@@ -406,39 +404,40 @@ void conv_bwd_weight(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<
   gemm(n, pw, ws.M, ws.N, splits, pick_tile_split(ws.M, ws.N));
 }
 
-// weight and bias gradients of a conv layer, then (if din.p) its data gradient
+// Weight and bias gradients of a conv layer from its output gradient dout
+// (stored masked by the layer's ReLU), and (if din.p) its data gradient,
+// stored masked by dmask > 0 (the output of the layer that produced the
+// input) on channels >= mc0; no mask when dmask.p is null.
 template <int KS, bool RELU>
-int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> act, View<const bf16> dout,
-               View<bf16> din) {
+int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const bf16> dout, View<bf16> din,
+               View<const bf16> dmask, int mc0) {
   const int P = g.B * g.H * g.W;
   const int Kw = KS * KS * c.Cin;
   const bool wdirect = KS == 3 && RELU && direct_ok(n, g, c.Cin, c.Cout, true);
   const bool ddirect = din.p && KS == 3 && RELU && direct_ok(n, g, c.Cout, c.Cin, false);
-  // with both gradients direct, the data gradient (first) leaves the BF16
-  // operand (output gradient x mask) of every pixel for the weight gradient
-  bf16 *dpre = (wdirect && ddirect) ? n->dpre : nullptr;
   if (din.p) {
     if (ddirect) {
       DConv pd{};
       pd.g = g;
       pd.T = DTiles::make(g.B, g.H, g.W);
       pd.dx = dout;
-      pd.act = act;
       pd.Kc = c.Cout;
       pd.Nc = c.Cin;
       pd.Wk = c.WtT;
       pd.dy = din;
-      pd.dpre = dpre;
+      pd.dmask = dmask;
+      pd.mc0 = mc0;
       launch_dconv<true, false>(n, pd);
     } else {
-      ConvBwdData<KS, RELU> pd;
+      ConvBwdData<KS> pd;
       pd.g = g;
       pd.dout = dout;
-      pd.act = act;
       pd.Cin = c.Cin;
       pd.Cout = c.Cout;
       pd.WtT = c.WtT;
       pd.din = din;
+      pd.mask = dmask;
+      pd.mc0 = mc0;
       pd.dCout = Div::make(c.Cout);
       gemm(n, pd, P, c.Cin, 1, pick_tile(P, c.Cin, 0));
     }
@@ -448,22 +447,18 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     pw.g = g;
     pw.T = DTiles::make(g.B, g.H, g.W);
     pw.dout = dout;
-    pw.act = act;
     pw.in = in;
     pw.Cin = c.Cin;
     pw.Cout = c.Cout;
-    pw.dpre = dpre;
     int splits;
     direct_wplan(pw.T.n, c.Cin, c.Cout, splits, pw.tps);
     pw.partial = take_partials(n, splits, c.Cout, Kw);
     if (!pw.partial) return fail(WS_EINVAL, "split scratch too small");
     const int hw = direct_whw(c.Cin);
     const dim3 grid((unsigned)splits, (unsigned)(c.Cout / 32), (unsigned)std::max(1, c.Cin / (16 * hw)));
-    if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1, false>), grid, dim3(128), 0, n->stream, pw);
-    else if (hw == 2 && dpre) hipLaunchKernelGGL((k_dwgrad<false, 2, true>), grid, dim3(256), 0, n->stream, pw);
-    else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2, false>), grid, dim3(256), 0, n->stream, pw);
-    else if (dpre) hipLaunchKernelGGL((k_dwgrad<false, 4, true>), grid, dim3(512), 0, n->stream, pw);
-    else hipLaunchKernelGGL((k_dwgrad<false, 4, false>), grid, dim3(512), 0, n->stream, pw);
+    if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1>), grid, dim3(128), 0, n->stream, pw);
+    else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2>), grid, dim3(256), 0, n->stream, pw);
+    else hipLaunchKernelGGL((k_dwgrad<false, 4>), grid, dim3(512), 0, n->stream, pw);
     queue_split_reduce(n, pw.partial, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   } else {
     const WShape ws = wshape(c.Cout, Kw + 1);
@@ -471,8 +466,8 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     split_plan(P, ws.M, ws.N, splits, chunk);
     float *part = take_partials(n, splits, c.Cout, Kw);
     if (!part) return fail(WS_EINVAL, "split scratch too small");
-    if (ws.tr) conv_bwd_weight<KS, RELU, true>(n, c, g, in, act, dout, chunk, splits, ws, part);
-    else conv_bwd_weight<KS, RELU, false>(n, c, g, in, act, dout, chunk, splits, ws, part);
+    if (ws.tr) conv_bwd_weight<KS, true>(n, c, g, in, dout, chunk, splits, ws, part);
+    else conv_bwd_weight<KS, false>(n, c, g, in, dout, chunk, splits, ws, part);
     queue_split_reduce(n, part, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   }
   return WS_OK;
@@ -573,6 +568,7 @@ int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const bf16
   pd.Cout = u.Cout;
   pd.WtT = u.WtT;
   pd.din = din;
+  pd.mask = in;  // the up-sampling input is a ReLU output: its gradient is stored masked
   pd.dCout = Div::make(u.Cout);
   gemm(n, pd, P, u.Cin, 1, pick_tile(P, u.Cin, 0));
   return WS_OK;
@@ -683,17 +679,18 @@ int backward(ws_net *n, const float *target, int B) {
     nlb = (int)blocks(P);
     hipLaunchKernelGGL(k_mse, dim3(nlb), dim3(256), 0, n->stream, n->y.p, target, P, n->cfg.cout, n->dy.p,
                        n->loss_part);
-    rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), View<const bf16>{nullptr, 0, 0}, cv(n->dy),
-                              mv(n->ddec[0]));
+    rc = conv_bwd_t<1, false>(n, n->head, g0, cv(n->dec[0]), cv(n->dy), mv(n->ddec[0]), cv(n->dec[0]), 0);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, n->stream, n->loss_part, nlb,
                      1.0 / ((double)P * n->cfg.cout), n->loss);
   for (int l = 0; l <= L - 2; ++l) {
     Img gl = Img::make(B, imgH(n, l), imgW(n, l)), gu = Img::make(B, imgH(n, l + 1), imgW(n, l + 1));
-    rc = conv_bwd_t<3, true>(n, n->d2[l], gl, cv(n->mid_d[l]), cv(n->dec[l]), cv(n->ddec[l]), mv(n->dmid_d[l]));
+    rc = conv_bwd_t<3, true>(n, n->d2[l], gl, cv(n->mid_d[l]), cv(n->ddec[l]), mv(n->dmid_d[l]), cv(n->mid_d[l]), 0);
     if (rc) return rc;
-    rc = conv_bwd_t<3, true>(n, n->d1[l], gl, cv(n->cat[l]), cv(n->mid_d[l]), cv(n->dmid_d[l]), mv(n->dcat[l]));
+    // the concatenation [up-sampled | skip]: only the skip part is a ReLU output
+    rc = conv_bwd_t<3, true>(n, n->d1[l], gl, cv(n->cat[l]), cv(n->dmid_d[l]), mv(n->dcat[l]), cv(n->cat[l]),
+                             n->up[l].Cout);
     if (rc) return rc;
     View<const bf16> uin = l == L - 2 ? cv(n->bott) : cv(n->dec[l + 1]);
     View<bf16> dup = l == L - 2 ? mv(n->dbott) : mv(n->ddec[l + 1]);
@@ -703,13 +700,13 @@ int backward(ws_net *n, const float *target, int B) {
   for (int l = L - 1; l >= 0; --l) {
     Img g = Img::make(B, imgH(n, l), imgW(n, l));
     const int C = chans(n, l);
-    View<const bf16> eout = l < L - 1 ? cv(n->cat[l], C) : cv(n->bott);
     View<const bf16> deout = l < L - 1 ? cv(n->dcat[l], C) : cv(n->dbott);
-    rc = conv_bwd_t<3, true>(n, n->e2[l], g, cv(n->mid_e[l]), eout, deout, mv(n->dmid_e[l]));
+    rc = conv_bwd_t<3, true>(n, n->e2[l], g, cv(n->mid_e[l]), deout, mv(n->dmid_e[l]), cv(n->mid_e[l]), 0);
     if (rc) return rc;
     View<const bf16> in = l == 0 ? cv(n->xin) : cv(n->pool[l]);
     View<bf16> din = l == 0 ? View<bf16>{nullptr, 0, 0} : mv(n->dpool[l]);
-    rc = conv_bwd_t<3, true>(n, n->e1[l], g, in, cv(n->mid_e[l]), cv(n->dmid_e[l]), din);
+    // the pooled input is no ReLU output: the pooling backward applies the mask
+    rc = conv_bwd_t<3, true>(n, n->e1[l], g, in, cv(n->dmid_e[l]), din, View<const bf16>{nullptr, 0, 0}, 0);
     if (rc) return rc;
     if (l > 0) {  // route the pooled gradient into the level l-1 encoder output
       Img gp = Img::make(B, imgH(n, l - 1), imgW(n, l - 1));
@@ -870,8 +867,6 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   }
   n->scratch_floats = worst;
   if (!rc) rc = dalloc(n, &n->scratch, worst);
-  // the largest direct layer's output gradient: C_l channels on H W / 4^l pixels
-  if (!rc) rc = dalloc(n, &n->dpre, c->conv_algo == 0 ? (size_t)c->max_batch * c->H * c->W * c->base : 1);
   n->n_loss_blocks = (int)blocks((int64_t)c->max_batch * c->H * c->W);  // k_mse: a pixel per thread
   if (!rc) rc = dalloc(n, &n->loss_part, n->n_loss_blocks);
   if (!rc) rc = dalloc(n, &n->loss, 1);
