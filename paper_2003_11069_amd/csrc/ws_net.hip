@@ -287,9 +287,10 @@ void launch_dconv_nw(ws_net *n, DConv p) {
   const int want = std::max(1, 512 / (nb * NW));
   p.tpb = std::max(1, (p.T.n + want - 1) / want);
   dim3 grid((unsigned)((p.T.n + p.tpb - 1) / p.tpb), (unsigned)nb);
-  // the forward stages a single slice's weights once (measured faster: 24.9 ->
-  // 20.1 us at level 0); the data gradient measured slower that way (32 -> 39)
-  if (!BWD && (C8 || p.Kc == 32))
+  // a single slice's weights are staged once (measured faster: forward 24.9 ->
+  // 20.1 us at level 0; data gradient, with its operand stored masked, 1.308
+  // -> 1.301 ms per training step)
+  if (C8 || p.Kc == 32)
     hipLaunchKernelGGL((k_dconv<BWD, C8, NW, true>), grid, dim3(256 * NW), 0, n->stream, p);
   else hipLaunchKernelGGL((k_dconv<BWD, C8, NW, false>), grid, dim3(256 * NW), 0, n->stream, p);
 }
