@@ -27,10 +27,12 @@ order is: encoder levels 0..L-1 (e1.W, e1.b, e2.W, e2.b), decoder levels
 L-2..0 (up.W, up.b, d1.W, d1.b, d2.W, d2.b), head (W, b).
 
 Precision.  With ``rounding=True`` values are rounded to bfloat16 (round to
-nearest even) exactly where the GPU stores BF16 -- the packed input, every
-weight, every hidden layer output after bias and ReLU, and each backward
-operand (output gradient times the ReLU mask) -- and everything else is FP64,
-so the remaining GPU difference is FP32 accumulation.  With
+nearest even) where the GPU stores BF16 -- the packed input, every weight,
+every hidden layer output after bias and ReLU, and each backward operand
+(output gradient times the ReLU mask) -- and everything else is FP64, so the
+remaining GPU difference is FP32 accumulation, plus two roundings the GPU
+adds on the pooling path (it stores the pooled gradient, and the sum of the
+skip and pooled gradients, in BF16; here both stay FP64).  With
 ``rounding=False`` the network is plain FP64 (used for finite differences).
 
 Parity: pinned by finite differences of the FP64 loss (all parameters and
