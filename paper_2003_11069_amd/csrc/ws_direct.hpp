@@ -294,6 +294,13 @@ struct DWGrad {
 constexpr int WA_P = DT_H * DT_W + 8;  // co pitch (bf16) of the transposed output gradient: 528 B
 constexpr int WB_R = 40;               // row pitch of the transposed input (34 columns used)
 constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
+// Each group of 8 channels starts a further WA_O / WB_O bf16 on: eight rows
+// of either pitch span a multiple of the 32 banks, so without it the staging
+// writes of the 4 (8) channel groups in one instruction all hit the same
+// banks; with it they land 16 (8) banks apart.
+constexpr int WA_O = 32, WB_O = 16;
+__device__ __forceinline__ int wa_row(int co) { return co * WA_P + (co >> 3) * WA_O; }
+__device__ __forceinline__ int wb_row(int ci) { return ci * WB_P + (ci >> 3) * WB_O; }
 
 // Block (split, 32 output channels, 16 HW input channels; HW = 1 for the
 // padded network input, whose channels 8..15 are staged as zeros), 2 HW
@@ -303,8 +310,8 @@ constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
 template <bool C8, int HW>
 __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
   constexpr int CI = 16 * HW, NTH = 128 * HW;
-  __shared__ __attribute__((aligned(16))) bf16 As[32 * WA_P];  // dPre^T [co][r][c]
-  __shared__ __attribute__((aligned(16))) bf16 Bs[CI * WB_P];  // in^T [ci][rr][cc], pixel (y0+rr-1, x0+cc-1)
+  __shared__ __attribute__((aligned(16))) bf16 As[32 * WA_P + 4 * WA_O];        // dPre^T [co][r][c]
+  __shared__ __attribute__((aligned(16))) bf16 Bs[CI * WB_P + CI / 8 * WB_O];   // in^T [ci][rr][cc], pixel (y0+rr-1, x0+cc-1)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
   const int mt = wave & 1, h = wave >> 1;
   const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * CI;
@@ -356,7 +363,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
       const int cq = q & 3, pp = q >> 2, r = pp >> 4, c = 2 * (pp & 15);
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * WA_P + r * DT_W + c]) = pack_bf16(ga[it][0][j], ga[it][1][j]);
+        *reinterpret_cast<uint32_t *>(&As[wa_row(8 * cq + j) + r * DT_W + c]) = pack_bf16(ga[it][0][j], ga[it][1][j]);
     }
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
@@ -365,7 +372,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
         const int cq = q % NCH, pp = q / NCH, rr = pp / (DW / 2), cc = 2 * (pp - rr * (DW / 2));
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          *reinterpret_cast<uint32_t *>(&Bs[(8 * cq + j) * WB_P + rr * WB_R + cc]) = pack_bf16(ib[it][0][j], ib[it][1][j]);
+          *reinterpret_cast<uint32_t *>(&Bs[wb_row(8 * cq + j) + rr * WB_R + cc]) = pack_bf16(ib[it][0][j], ib[it][1][j]);
       }
     }
   };
@@ -383,10 +390,10 @@ __global__ __launch_bounds__(128 * HW, 2) void k_dwgrad(DWGrad P) {
 #pragma unroll
       for (int rr = 0; rr < DH; ++rr) {
         if (rr < DT_H) {
-          a[rr] = *reinterpret_cast<const bf16x8 *>(&As[(16 * mt + l16) * WA_P + rr * DT_W + 8 * g]);
+          a[rr] = *reinterpret_cast<const bf16x8 *>(&As[wa_row(16 * mt + l16) + rr * DT_W + 8 * g]);
           if (h == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rr], ones, accb, 0, 0, 0);
         }
-        const bf16 *src = &Bs[(16 * h + l16) * WB_P + rr * WB_R + 8 * g];
+        const bf16 *src = &Bs[wb_row(16 * h + l16) + rr * WB_R + 8 * g];
         const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
         const uint32_t hi = *reinterpret_cast<const uint32_t *>(src + 8);
         u32x4 s1, s2;  // windows starting one and two pixels further right
@@ -442,14 +449,17 @@ struct DUpW {
   float *partial;
 };
 constexpr int UW_K = 128, UW_P = UW_K + 8;  // input pixels per item; LDS pitch (bf16)
+// channel groups of 8 offset as in k_dwgrad (the pitch times 8 spans whole bank rows)
+__device__ __forceinline__ int uwa_row(int co) { return co * UW_P + (co >> 3) * 32; }
+__device__ __forceinline__ int uwb_row(int ci) { return ci * UW_P + (ci >> 3) * 16; }
 
 template <int HW>
 __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
   constexpr int CI = 16 * HW, NTH = 128 * HW;
   constexpr int AN = UW_K / 2 * 4, AIT = (AN + NTH - 1) / NTH;  // pixel pairs x 8-channel chunks
   constexpr int BNI = UW_K / 2 * (CI / 8), BIT = (BNI + NTH - 1) / NTH;
-  __shared__ __attribute__((aligned(16))) bf16 As[32 * UW_P];  // dOut^T [co][px]
-  __shared__ __attribute__((aligned(16))) bf16 Bs[CI * UW_P];  // in^T [ci][px]
+  __shared__ __attribute__((aligned(16))) bf16 As[32 * UW_P + 4 * 32];       // dOut^T [co][px]
+  __shared__ __attribute__((aligned(16))) bf16 Bs[CI * UW_P + CI / 8 * 16];  // in^T [ci][px]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
   const int mt = wave & 1, h = wave >> 1;
   const int cot = P.Cout / 32, d = blockIdx.y / cot, co0 = (blockIdx.y % cot) * 32, ci0 = blockIdx.z * CI;
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
         const int cq = q & 3, k = 2 * (q >> 2);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          *reinterpret_cast<uint32_t *>(&As[(8 * cq + j) * UW_P + k]) = pack_bf16(ga[a][0][j], ga[a][1][j]);
+          *reinterpret_cast<uint32_t *>(&As[uwa_row(8 * cq + j) + k]) = pack_bf16(ga[a][0][j], ga[a][1][j]);
       }
     }
 #pragma unroll
@@ -516,7 +526,7 @@ __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
         const int cq = q % (CI / 8), k = 2 * (q / (CI / 8));
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          *reinterpret_cast<uint32_t *>(&Bs[(8 * cq + j) * UW_P + k]) = pack_bf16(ib[a][0][j], ib[a][1][j]);
+          *reinterpret_cast<uint32_t *>(&Bs[uwb_row(8 * cq + j) + k]) = pack_bf16(ib[a][0][j], ib[a][1][j]);
       }
     }
   };
@@ -528,8 +538,8 @@ __global__ __launch_bounds__(128 * HW, 2) void k_upwgrad(DUpW P) {
     if (it + 1 < i1) gload(it + 1);
 #pragma unroll
     for (int ks = 0; ks < UW_K / 32; ++ks) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[(16 * mt + l16) * UW_P + 32 * ks + 8 * g]);
-      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[(16 * h + l16) * UW_P + 32 * ks + 8 * g]);
+      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[uwa_row(16 * mt + l16) + 32 * ks + 8 * g]);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[uwb_row(16 * h + l16) + 32 * ks + 8 * g]);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
       if (h == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb, 0, 0, 0);
     }
