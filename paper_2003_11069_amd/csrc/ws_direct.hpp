@@ -91,7 +91,9 @@ struct DConv {
 // walks (tile, 32-channel slice) items; the global loads of item i + 1 are
 // issued before the MFMAs of item i and land in registers, all of an item's
 // loads together, so memory latency overlaps the MFMAs.
-template <bool BWD, bool C8, int NW, bool SL1>
+// SW = 1, 2: the weights of all (at most SW) 32-channel slices are staged
+// once per block; SW = 0: each item stages its slice's weights.
+template <bool BWD, bool C8, int NW, int SW>
 __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
   constexpr int NT = 2, BN = 32 * NW, NTH = 256 * NW;
   constexpr int XP = C8 ? 8 : DP;  // the padded input has one 8-channel chunk per pixel
@@ -102,11 +104,12 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
   constexpr int OP = 32 + 8;  // pixel pitch of the output staged through Xs
   constexpr int XS = DH * DW * XP > 4 * NW * 64 * OP ? DH * DW * XP : 4 * NW * 64 * OP;
   __shared__ __attribute__((aligned(16))) bf16 Xs[XS];
-  __shared__ __attribute__((aligned(16))) bf16 Ws[NWS * BN * DP];
+  constexpr int WSL = NWS * BN * DP;  // one slice's weights (bf16)
+  __shared__ __attribute__((aligned(16))) bf16 Ws[WSL * (SW > 0 ? SW : 1)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
   const int rg = wave & 3, ng = wave >> 2;  // row pair, N group
   const int n0 = blockIdx.y * BN, nw0 = n0 + 32 * ng, H = P.g.H, W = P.g.W;
-  const int slices = (C8 || SL1) ? 1 : P.Kc / 32;  // SL1: one 32-channel slice (weights staged once)
+  const int slices = (C8 || SW == 1) ? 1 : P.Kc / 32;
   const int blk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int t0 = blk * P.tpb, t1 = min(P.T.n, t0 + P.tpb);
   const int items = (t1 - t0) * slices;
@@ -146,13 +149,13 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       }
     }
   };
-  auto wstore = [&]() {
+  auto wstore = [&](int sd) {
 #pragma unroll
     for (int it = 0; it < WIT; ++it) {
       const int q = tid + NTH * it;
       if (q < WN) {
         const int gq = q & 3, n = (q >> 2) % BN, w = (q >> 2) / BN;
-        *reinterpret_cast<bf16x8 *>(&Ws[(w * BN + n) * DP + 8 * gq]) = wr[it];
+        *reinterpret_cast<bf16x8 *>(&Ws[sd * WSL + (w * BN + n) * DP + 8 * gq]) = wr[it];
       }
     }
   };
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       const bool in = q < XN && yy >= 0 && yy < H && xx >= 0 && xx < W;
       xa[it] = in ? *reinterpret_cast<const bf16x8 *>(xb + rel[it] * X.cs + ch) : zero8();
     }
-    if (!SL1) wload(s);
+    if (!SW) wload(s);
   };
   // backward-data: the output mask of the tile's 16-byte output rows (four per
   // lane, as the epilogue stores them), loaded before the next item's staging
@@ -202,11 +205,13 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
         *reinterpret_cast<bf16x8 *>(&Xs[pix * XP + ch]) = xa[it];
       }
     }
-    if (!SL1) wstore();
+    if (!SW) wstore(0);
   };
-  if (SL1 && items > 0) {  // the one slice's weights, staged once
-    wload(0);
-    wstore();
+  if (SW && items > 0) {  // every slice's weights, staged once
+    for (int sl = 0; sl < slices; ++sl) {
+      wload(sl);
+      wstore(sl);
+    }
   }
   if (items > 0) gload(0);
   for (int item = 0; item < items; ++item) {
@@ -215,6 +220,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
     __syncthreads();
     if (BWD && P.dmask.p && item % slices == slices - 1) mload(item);
     if (item + 1 < items) gload(item + 1);
+    const bf16 *Wsl = Ws + (SW ? (item % slices) * WSL : 0);
 #pragma unroll
     for (int w = 0; w < NWS; ++w) {
       int ky, kx;
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       bf16x8 bw[NT];
 #pragma unroll
       for (int j = 0; j < NT; ++j)
-        bw[j] = *reinterpret_cast<const bf16x8 *>(&Ws[(w * BN + 32 * ng + 16 * j + l16) * DP + 8 * g]);
+        bw[j] = *reinterpret_cast<const bf16x8 *>(&Wsl[(w * BN + 32 * ng + 16 * j + l16) * DP + 8 * g]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = 2 * rg + (i >> 1), col = 16 * (i & 1) + l16;

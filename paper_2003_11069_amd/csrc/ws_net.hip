@@ -287,12 +287,15 @@ void launch_dconv_nw(ws_net *n, DConv p) {
   const int want = std::max(1, 512 / (nb * NW));
   p.tpb = std::max(1, (p.T.n + want - 1) / want);
   dim3 grid((unsigned)((p.T.n + p.tpb - 1) / p.tpb), (unsigned)nb);
-  // a single slice's weights are staged once (measured faster: forward 24.9 ->
-  // 20.1 us at level 0; data gradient, with its operand stored masked, 1.308
-  // -> 1.301 ms per training step)
+  // the weights of one or two 32-channel slices are staged once per block
+  // (one slice: forward 24.9 -> 20.1 us at level 0, data gradient 1.308 ->
+  // 1.301 ms per training step; two: 1.256 -> 1.243 ms); more slices reload
+  // each item's
   if (C8 || p.Kc == 32)
-    hipLaunchKernelGGL((k_dconv<BWD, C8, NW, true>), grid, dim3(256 * NW), 0, n->stream, p);
-  else hipLaunchKernelGGL((k_dconv<BWD, C8, NW, false>), grid, dim3(256 * NW), 0, n->stream, p);
+    hipLaunchKernelGGL((k_dconv<BWD, C8, NW, 1>), grid, dim3(256 * NW), 0, n->stream, p);
+  else if (p.Kc == 64)
+    hipLaunchKernelGGL((k_dconv<BWD, C8, NW, 2>), grid, dim3(256 * NW), 0, n->stream, p);
+  else hipLaunchKernelGGL((k_dconv<BWD, C8, NW, 0>), grid, dim3(256 * NW), 0, n->stream, p);
 }
 
 template <bool BWD, bool C8>
