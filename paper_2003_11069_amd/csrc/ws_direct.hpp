@@ -301,10 +301,12 @@ constexpr int WA_P = DT_H * DT_W + 8;  // co pitch (bf16) of the transposed outp
 constexpr int WB_R = 40;               // row pitch of the transposed input (34 columns used)
 constexpr int WB_P = DH * WB_R + 8;    // ci pitch: 816 B
 // Each group of 8 channels starts a further WA_O / WB_O bf16 on: eight rows
-// of either pitch span a multiple of the 32 banks, so without it the staging
-// writes of the 4 (8) channel groups in one instruction all hit the same
-// banks; with it they land 16 (8) banks apart.
-constexpr int WA_O = 32, WB_O = 16;
+// of either pitch span a whole number of bank rows, so without it the
+// staging writes of the 4 (8) channel groups in one instruction all hit the
+// same banks.  Measured per training step: weight gradients 411 us without
+// the offsets, 371 with 32 / 16, 360 with 16 / 8 (8 / 8, 24 / 8 and 16 / 24
+// within 4 us of it, 64 / 32 slower).
+constexpr int WA_O = 16, WB_O = 8;
 __device__ __forceinline__ int wa_row(int co) { return co * WA_P + (co >> 3) * WA_O; }
 __device__ __forceinline__ int wb_row(int ci) { return ci * WB_P + (ci >> 3) * WB_O; }
 
