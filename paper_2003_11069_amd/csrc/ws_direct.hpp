@@ -79,6 +79,7 @@ struct DConv {
   const bf16 *Wk;        // [Nc][9][Kc]
   const float *bias;     // forward
   View<bf16> y;          // forward output (Nc channels)
+  View<bf16> pool;       // forward: when set, also its 2x2 max pooling (Nc channels)
   View<bf16> dy;         // backward-data output (stored, not added)
   View<const bf16> dmask;  // backward-data: output of the input's producer; dy
   int mc0;                 // is zeroed where it is not positive, channels >= mc0
@@ -281,6 +282,20 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
         for (int j = 0; j < 8; ++j) v[j] = (float)mk[k][j] > 0.f ? v[j] : (bf16)0.f;
       }
       *reinterpret_cast<bf16x8 *>(Y.p + p * Y.cs + Y.coff + n0 + 32 * ng + c8) = v;
+    }
+    if (!BWD && P.pool.p) {
+      // the wave's two rows are one row of 2x2 windows (y0 and the row pair
+      // are even): lane = (pooled pixel of 16, 8-channel chunk)
+      const int px = lane >> 2, c8 = (lane & 3) * 8;
+      bf16x8 m = *reinterpret_cast<const bf16x8 *>(&O[(2 * px) * OP + c8]);
+#pragma unroll
+      for (int d = 1; d < 4; ++d) {
+        const bf16x8 o = *reinterpret_cast<const bf16x8 *>(&O[(32 * (d >> 1) + 2 * px + (d & 1)) * OP + c8]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) m[j] = (float)o[j] > (float)m[j] ? o[j] : m[j];
+      }
+      const size_t q = ((size_t)b * (H / 2) + (y0 / 2 + rg)) * (W / 2) + x0 / 2 + px;
+      *reinterpret_cast<bf16x8 *>(P.pool.p + q * P.pool.cs + P.pool.coff + n0 + 32 * ng + c8) = m;
     }
   }
 }

@@ -320,7 +320,11 @@ int conv_fwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> 
   return WS_OK;
 }
 
-int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> out) {
+// pool.p set: also writes the output's 2x2 max pooling there when the direct
+// kernel runs (*pooled = true), else leaves it to the caller.
+int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> out,
+             View<bf16> pool = View<bf16>{nullptr, 0, 0}, bool *pooled = nullptr) {
+  if (pooled) *pooled = false;
   if (c.KS == 3 && c.relu && direct_ok(n, g, c.Cin, c.Cout, true)) {
     DConv p{};
     p.g = g;
@@ -331,6 +335,8 @@ int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> ou
     p.Wk = c.Wt;
     p.bias = n->params + c.b_off;
     p.y = out;
+    p.pool = pool;
+    if (pooled) *pooled = pool.p != nullptr;
     if (c.Cin == 8) launch_dconv<false, true>(n, p);
     else launch_dconv<false, false>(n, p);
     return WS_OK;
@@ -613,9 +619,11 @@ int forward(ws_net *n, const float *x, int B, bool head = true) {
     int rc = conv_fwd(n, n->e1[l], g, in, mv(n->mid_e[l]));
     if (rc) return rc;
     View<bf16> eout = l < L - 1 ? mv(n->cat[l], C) : mv(n->bott);
-    rc = conv_fwd(n, n->e2[l], g, cv(n->mid_e[l]), eout);
+    bool pooled = false;
+    rc = conv_fwd(n, n->e2[l], g, cv(n->mid_e[l]), eout, l < L - 1 ? mv(n->pool[l + 1]) : View<bf16>{nullptr, 0, 0},
+                  &pooled);
     if (rc) return rc;
-    if (l < L - 1) {
+    if (l < L - 1 && !pooled) {
       const int64_t cnt = (int64_t)B * (g.H / 2) * (g.W / 2) * (C / 8);  // 8 channels per thread
       hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, g,
                          View<const bf16>{eout.p, eout.cs, eout.coff}, C, mv(n->pool[l + 1]));
