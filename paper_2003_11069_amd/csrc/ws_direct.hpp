@@ -9,7 +9,8 @@
 // ws_kernels.hpp gathers every tap from global memory, and converts a
 // backward operand once per tap).
 //
-//   k_dconv      forward (BF16 input; bias, ReLU, BF16 output) and
+//   k_dconv      forward (BF16 input; bias, ReLU, BF16 output, optionally
+//                also its 2x2 max pooling) and
 //                backward-data (the layer's output gradient, stored already
 //                masked by its ReLU; BF16 output, masked by the ReLU of the
 //                input's producer).  The staged operand
