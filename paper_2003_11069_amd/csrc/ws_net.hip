@@ -98,6 +98,14 @@ struct ws_net {
   float *scratch = nullptr;
   size_t scratch_floats = 0, scratch_used = 0;
   std::vector<WJob> jobs;
+  // weight gradients run on a second stream (default priority), each after
+  // an event on the network's stream that marks its output gradient final,
+  // beside the data gradients; joined before the split sums
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> evs;  // fork events, reused every pass
+  hipEvent_t ev_join = nullptr;
+  size_t ev_next = 0;
+  bool on_side = false, side_pending = false;
   double *loss_part = nullptr, *loss = nullptr;
   int n_loss_blocks = 0;
   std::vector<void *> allocs;
@@ -215,7 +223,7 @@ template <class Prob, int BMt, int BNt>
 void launch(ws_net *n, const Prob &p, int M, int N, int splits) {
   constexpr int KB = (BMt == DeepK<Prob>::bm && BNt == DeepK<Prob>::bn) ? 64 : BK;
   dim3 grid((M + BMt - 1) / BMt, (N + BNt - 1) / BNt, splits);
-  hipLaunchKernelGGL((k_gemm<Prob, BMt, BNt, KB>), grid, dim3(256), 0, n->stream, p);
+  hipLaunchKernelGGL((k_gemm<Prob, BMt, BNt, KB>), grid, dim3(256), 0, n->on_side ? n->side : n->stream, p);
 }
 
 template <class Prob>
@@ -363,6 +371,32 @@ float *take_partials(ws_net *n, int splits, int M, int Kw) {
   return p;
 }
 
+// side_mark records the network's stream's progress; weight-gradient
+// launches between side_begin(that mark) and side_end go to the side stream,
+// after everything queued before the mark.  Out of events: no side stream.
+hipEvent_t side_mark(ws_net *n) {
+  if (n->ev_next >= n->evs.size()) return nullptr;
+  hipEvent_t e = n->evs[n->ev_next++];
+  return hipEventRecord(e, n->stream) == hipSuccess ? e : nullptr;
+}
+int side_begin(ws_net *n, hipEvent_t mark) {
+  if (!mark) return WS_OK;
+  HTRY(hipStreamWaitEvent(n->side, mark, 0));
+  n->on_side = n->side_pending = true;
+  return WS_OK;
+}
+void side_end(ws_net *n) { n->on_side = false; }
+// The network's stream waits for every weight gradient.
+int side_join(ws_net *n) {
+  if (n->side_pending) {
+    HTRY(hipEventRecord(n->ev_join, n->side));
+    HTRY(hipStreamWaitEvent(n->stream, n->ev_join, 0));
+  }
+  n->side_pending = false;
+  n->ev_next = 0;
+  return WS_OK;
+}
+
 // Queues the sum of partials [splits][M][Kw+1] into dW [M][Kw] and the bias
 // column into db: row m's bias when Cb = M, else db[c] = sum over rows
 // m = c (mod Cb).
@@ -425,6 +459,7 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
   const int Kw = KS * KS * c.Cin;
   const bool wdirect = KS == 3 && RELU && direct_ok(n, g, c.Cin, c.Cout, true);
   const bool ddirect = din.p && KS == 3 && RELU && direct_ok(n, g, c.Cout, c.Cin, false);
+  hipEvent_t mark = side_mark(n);  // dout is final: the weight gradient may start beside the data gradient
   if (din.p) {
     if (ddirect) {
       DConv pd{};
@@ -452,6 +487,8 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
       gemm(n, pd, P, c.Cin, 1, pick_tile(P, c.Cin, 0));
     }
   }
+  if (int e = side_begin(n, mark)) return e;
+  const hipStream_t wst = n->on_side ? n->side : n->stream;
   if (wdirect) {
     DWGrad pw{};
     pw.g = g;
@@ -466,9 +503,9 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     if (!pw.partial) return fail(WS_EINVAL, "split scratch too small");
     const int hw = direct_whw(c.Cin);
     const dim3 grid((unsigned)splits, (unsigned)(c.Cout / 32), (unsigned)std::max(1, c.Cin / (16 * hw)));
-    if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1>), grid, dim3(128), 0, n->stream, pw);
-    else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2>), grid, dim3(256), 0, n->stream, pw);
-    else hipLaunchKernelGGL((k_dwgrad<false, 4>), grid, dim3(512), 0, n->stream, pw);
+    if (hw == 1) hipLaunchKernelGGL((k_dwgrad<true, 1>), grid, dim3(128), 0, wst, pw);
+    else if (hw == 2) hipLaunchKernelGGL((k_dwgrad<false, 2>), grid, dim3(256), 0, wst, pw);
+    else hipLaunchKernelGGL((k_dwgrad<false, 4>), grid, dim3(512), 0, wst, pw);
     queue_split_reduce(n, pw.partial, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   } else {
     const WShape ws = wshape(c.Cout, Kw + 1);
@@ -480,6 +517,7 @@ int conv_bwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<const 
     else conv_bwd_weight<KS, false>(n, c, g, in, dout, chunk, splits, ws, part);
     queue_split_reduce(n, part, splits, c.Cout, Kw, n->grads + c.w_off, n->grads + c.b_off, c.Cout);
   }
+  side_end(n);
   return WS_OK;
 }
 
@@ -538,6 +576,8 @@ void up_wplan(const Img &gin, const Up &u, int &hw, int &splits, int &ipb) {
 
 int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const bf16> dout, View<bf16> din) {
   const int P = gin.B * gin.H * gin.W;
+  if (int e = side_begin(n, side_mark(n))) return e;
+  const hipStream_t wst = n->on_side ? n->side : n->stream;
   if (up_direct_wgrad(n, gin, u)) {
     DUpW pw{};
     pw.g = gin;
@@ -552,8 +592,8 @@ int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const bf16
     pw.partial = take_partials(n, splits, 4 * u.Cout, u.Cin);
     if (!pw.partial) return fail(WS_EINVAL, "split scratch too small");
     const dim3 grid((unsigned)splits, (unsigned)(4 * u.Cout / 32), (unsigned)(u.Cin / (16 * hw)));
-    if (hw == 4) hipLaunchKernelGGL(k_upwgrad<4>, grid, dim3(512), 0, n->stream, pw);
-    else hipLaunchKernelGGL(k_upwgrad<2>, grid, dim3(256), 0, n->stream, pw);
+    if (hw == 4) hipLaunchKernelGGL(k_upwgrad<4>, grid, dim3(512), 0, wst, pw);
+    else hipLaunchKernelGGL(k_upwgrad<2>, grid, dim3(256), 0, wst, pw);
     queue_split_reduce(n, pw.partial, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
   } else {
     int splits, chunk;
@@ -571,6 +611,7 @@ int up_bwd(ws_net *n, const Up &u, Img gin, View<const bf16> in, View<const bf16
     gemm(n, pw, 4 * u.Cout, u.Cin + 1, splits, pick_tile_split(4 * u.Cout, u.Cin + 1));
     queue_split_reduce(n, pw.partial, splits, 4 * u.Cout, u.Cin, n->grads + u.w_off, n->grads + u.b_off, u.Cout);
   }
+  side_end(n);
   UpBwdData pd;
   pd.g = gin;
   pd.dout = dout;
@@ -651,6 +692,7 @@ int forward(ws_net *n, const float *x, int B, bool head = true) {
 // Loss (into n->loss) and all gradients, after forward(n, x, B, !head_fused(n)).
 int backward(ws_net *n, const float *target, int B) {
   const int L = n->L;
+  if (int e = side_join(n)) return e;  // a pass that ended early may have left work on the side stream
   n->jobs.clear();
   n->scratch_used = 0;
   Img g0 = Img::make(B, n->cfg.H, n->cfg.W);
@@ -728,6 +770,8 @@ int backward(ws_net *n, const float *target, int B) {
                          cv(n->dpool[l]), mv(n->dcat[l - 1], Cp));
     }
   }
+  rc = side_join(n);
+  if (rc) return rc;
   flush_split_reduce(n);
   HTRY(hipGetLastError());
   return WS_OK;
@@ -764,6 +808,19 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   n->L = c->levels;
   n->C0 = c->base;
   n->stream = (hipStream_t)hip_stream;
+  {
+    bool ok = hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < 64; ++i) {
+      hipEvent_t e;
+      ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+      if (ok) n->evs.push_back(e);
+    }
+    if (!ok) {
+      ws_destroy(n);
+      return fail(WS_EDEVICE, "stream or event creation failed");
+    }
+  }
   const int L = n->L;
   int64_t off = 0;
   for (int l = 0; l < L; ++l) {
@@ -898,6 +955,12 @@ void ws_destroy(ws_net *n) {
   if (!n) return;
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   else (void)hipDeviceSynchronize();
+  if (n->side) {
+    (void)hipStreamSynchronize(n->side);
+    (void)hipStreamDestroy(n->side);
+  }
+  for (hipEvent_t e : n->evs) (void)hipEventDestroy(e);
+  if (n->ev_join) (void)hipEventDestroy(n->ev_join);
   for (void *p : n->allocs) (void)hipFree(p);
   delete n;
 }
