@@ -269,16 +269,16 @@ bool direct_ok(const ws_net *n, const Img &g, int Kc, int Nc, bool c8_ok) {
 int direct_whw(int Cin) { return Cin == 8 ? 1 : (Cin % 64 == 0 ? 4 : 2); }
 
 // Split plan of a direct weight gradient, each block summing a run of
-// tiles: 256 blocks of 4 or 8 waves (one per CU: registers and LDS hold one
-// 8-wave block per CU, so every block runs in the first round), 512 of the
-// 2-wave blocks of the padded input.  Measured per training step: 1.45 ms,
-// against 1.51 with 192 / 384 / 768 blocks (hw 4 / 2 / 1; a quarter of the
-// CUs idle), 1.53 with 512 / 768 / 1024 (a second round), 1.48 with 128
-// blocks at hw 2.
+// tiles: 192 blocks of 4 or 8 waves, 512 of the 2-wave blocks of the padded
+// input.  Alone on the GPU, 256 (one per CU: registers and LDS hold one
+// 8-wave block per CU) measured best (1.45 ms per training step, against
+// 1.51 with 192 / 384 / 768 blocks at hw 4 / 2 / 1 and 1.53 with a second
+// round); since the weight gradients run beside the data gradients, 192
+// leaves them room (1.152 ms with 256, 1.144 with 128, 1.130 with 192).
 void direct_wplan(int ntiles, int Cin, int Cout, int &splits, int &tps) {
   const int hw = direct_whw(Cin);
   const int combos = std::max(1, Cin / (16 * hw)) * (Cout / 32);
-  const int want = std::max(1, (hw == 1 ? 512 : 256) / combos);
+  const int want = std::max(1, (hw == 1 ? 512 : 192) / combos);
   tps = std::max(1, (ntiles + want - 1) / want);
   splits = (ntiles + tps - 1) / tps;
 }
@@ -413,7 +413,9 @@ void queue_split_reduce(ws_net *n, const float *partial, int splits, int M, int 
 }
 
 // Launches the queued sums, WJ_MAX layers per launch, and frees the scratch.
-void flush_split_reduce(ws_net *n) {
+// (on the side stream when `side`: after the weight gradients queued there;
+// the partials stay reserved until the pass ends)
+void flush_split_reduce(ws_net *n, bool side = false) {
   for (size_t i = 0; i < n->jobs.size(); i += WJ_MAX) {
     WJobs J{};
     int blk = 0;
@@ -427,10 +429,10 @@ void flush_split_reduce(ws_net *n) {
       blk += j.nbw + (j.Cb < rows ? (j.Cb + WR_G - 1) / WR_G : 0);
       J.j[J.n++] = j;
     }
-    hipLaunchKernelGGL(k_wreduce, dim3((unsigned)blk), dim3(64 * WR_G), 0, n->stream, J);
+    hipLaunchKernelGGL(k_wreduce, dim3((unsigned)blk), dim3(64 * WR_G), 0, side ? n->side : n->stream, J);
   }
   n->jobs.clear();
-  n->scratch_used = 0;
+  if (!side) n->scratch_used = 0;
 }
 
 template <int KS, bool TR>
@@ -751,6 +753,9 @@ int backward(ws_net *n, const float *target, int B) {
     rc = up_bwd(n, n->up[l], gu, uin, cv(n->dcat[l], 0), dup);
     if (rc) return rc;
   }
+  // the head's and decoder's sums, on the side stream after their weight
+  // gradients, beside the encoder's gradients
+  if (n->side_pending) flush_split_reduce(n, true);
   for (int l = L - 1; l >= 0; --l) {
     Img g = Img::make(B, imgH(n, l), imgW(n, l));
     const int C = chans(n, l);
