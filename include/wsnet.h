@@ -53,8 +53,11 @@
  *     arrays passed to ws_set_params / ws_get_params / ws_get_grads are HOST
  *     arrays of exactly ws_num_params() floats.
  *   - All work is queued on the network's HIP stream (given at ws_create;
- *     NULL = the null stream).  Calls that return data to the host
- *     synchronise that stream.
+ *     NULL = the null stream), so it is ordered against other work there.
+ *     The backward pass also runs its weight gradients on an internal stream
+ *     of default priority that forks from and joins back into that stream
+ *     (events), before the pass's last kernel.  Calls that return data to the
+ *     host synchronise the network's stream; ws_destroy synchronises both.
  *   - Every call returns 0 (WS_OK) or a negative WS_E* code; the message of
  *     the last failure on the calling thread is ws_last_error().
  *   - The network owns its device buffers, sized for max_batch images.
