@@ -106,6 +106,7 @@ struct ws_net {
   hipEvent_t ev_join = nullptr;
   size_t ev_next = 0;
   bool on_side = false, side_pending = false;
+  bool head_lds_set = false;  // the training head's dynamic LDS limit raised
   double *loss_part = nullptr, *loss = nullptr;
   int n_loss_blocks = 0;
   std::vector<void *> allocs;
@@ -722,8 +723,11 @@ int backward(ws_net *n, const float *target, int B) {
     switch (nt) {
 #define WS_HEAD(NT)                                                                                   \
   case NT:                                                                                            \
-    HTRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_head<NT>),                             \
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                  \
+    if (lds > 65536 && !n->head_lds_set) { /* once: more than the default dynamic LDS */             \
+      HTRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_head<NT>),                           \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                \
+      n->head_lds_set = true;                                                                         \
+    }                                                                                                 \
     hipLaunchKernelGGL(k_head<NT>, dim3(grid), dim3(256), lds, n->stream, h);                         \
     break;
       WS_HEAD(1) WS_HEAD(2) WS_HEAD(4) WS_HEAD(8) WS_HEAD(16)
