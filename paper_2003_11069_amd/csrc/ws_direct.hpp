@@ -81,6 +81,9 @@ struct DConv {
   const float *bias;     // forward
   View<bf16> y;          // forward output (Nc channels)
   View<bf16> pool;       // forward: when set, also its 2x2 max pooling (Nc channels)
+  uint8_t *parg;         // with pool: per pooled element the window position of
+                         // its first maximum (0..3), or 255 where that maximum
+                         // is not positive, [pooled pixel][Nc]
   View<bf16> dy;         // backward-data output (stored, not added)
   View<const bf16> dmask;  // backward-data: output of the input's producer; dy
   int mc0;                 // is zeroed where it is not positive, channels >= mc0
@@ -289,14 +292,26 @@ __global__ __launch_bounds__(256 * NW, 2) void k_dconv(DConv P) {
       // are even): lane = (pooled pixel of 16, 8-channel chunk)
       const int px = lane >> 2, c8 = (lane & 3) * 8;
       bf16x8 m = *reinterpret_cast<const bf16x8 *>(&O[(2 * px) * OP + c8]);
+      uint32_t arg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int d = 1; d < 4; ++d) {
         const bf16x8 o = *reinterpret_cast<const bf16x8 *>(&O[(32 * (d >> 1) + 2 * px + (d & 1)) * OP + c8]);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) m[j] = (float)o[j] > (float)m[j] ? o[j] : m[j];
+        for (int j = 0; j < 8; ++j)
+          if ((float)o[j] > (float)m[j]) {
+            m[j] = o[j];
+            arg[j] = d;
+          }
       }
       const size_t q = ((size_t)b * (H / 2) + (y0 / 2 + rg)) * (W / 2) + x0 / 2 + px;
       *reinterpret_cast<bf16x8 *>(P.pool.p + q * P.pool.cs + P.pool.coff + n0 + 32 * ng + c8) = m;
+      uint32_t lo = 0, hi = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        lo |= ((float)m[j] > 0.f ? arg[j] : 255u) << (8 * j);
+        hi |= ((float)m[j + 4] > 0.f ? arg[j + 4] : 255u) << (8 * j);
+      }
+      *reinterpret_cast<uint2 *>(P.parg + q * P.Nc + n0 + 32 * ng + c8) = make_uint2(lo, hi);
     }
   }
 }

@@ -561,7 +561,9 @@ static __global__ __launch_bounds__(256) void k_pool_fwd(Img g, View<const bf16>
 
 // Backward: a thread per pooled element (consecutive threads take consecutive
 // channels, so the read-modify-write of the maximum's element is coalesced;
-// 8-channel vectors measured slower here).
+// 8-channel vectors measured slower here).  Used after an implicit-GEMM
+// forward; after the direct forward, k_pool_bwd_arg reads the window
+// positions that forward recorded instead of the four activations.
 static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16> in, int C, View<const bf16> dout,
                                                   View<bf16> din) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -579,6 +581,22 @@ static __global__ __launch_bounds__(256) void k_pool_bwd(Img g, View<const bf16>
   const size_t q = ((size_t)b * g.H + 2 * y + (arg >> 1)) * g.W + 2 * x + (arg & 1);
   bf16 &d = din.p[q * din.cs + din.coff + c];
   d = (bf16)((float)d + (float)dout.p[(size_t)t * dout.cs + dout.coff + c]);
+}
+
+// Backward from the window positions the fused forward recorded (255: the
+// maximum was not positive, nothing to add): a thread per pooled element,
+// as k_pool_bwd, without reading the activations.
+static __global__ __launch_bounds__(256) void k_pool_bwd_arg(Img g, const uint8_t *arg, int C, View<const bf16> dout,
+                                                      View<bf16> din) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Ho = g.H / 2, Wo = g.W / 2;
+  if (i >= g.B * Ho * Wo * C) return;
+  const int d = arg[i];
+  if (d > 3) return;
+  const int c = i % C, t = i / C, x = t % Wo, t2 = t / Wo, y = t2 % Ho, b = t2 / Ho;
+  const size_t q = ((size_t)b * g.H + 2 * y + (d >> 1)) * g.W + 2 * x + (d & 1);
+  bf16 &v = din.p[q * din.cs + din.coff + c];
+  v = (bf16)((float)v + (float)dout.p[(size_t)t * dout.cs + dout.coff + c]);
 }
 
 // Network input: FP32 NHWC [P][cin] -> BF16 [P][8] (channels padded with

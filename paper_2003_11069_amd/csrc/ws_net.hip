@@ -87,6 +87,8 @@ struct ws_net {
   // activations (BF16) and gradients (FP32), per level
   Buf<bf16> xin;                 // packed input, 8 channels
   std::vector<Buf<bf16>> pool;   // pool output feeding level l (l >= 1)
+  std::vector<Buf<uint8_t>> parg;  // its argmax codes, when the forward fused the pooling
+  std::vector<char> pool_fused;    // per level: the last forward wrote parg
   std::vector<Buf<bf16>> mid_e, cat, mid_d, dec;
   Buf<bf16> bott;                // encoder output of the last level
   Buf<float> y;                  // head output, 8 channels
@@ -332,7 +334,7 @@ int conv_fwd_t(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> 
 // pool.p set: also writes the output's 2x2 max pooling there when the direct
 // kernel runs (*pooled = true), else leaves it to the caller.
 int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> out,
-             View<bf16> pool = View<bf16>{nullptr, 0, 0}, bool *pooled = nullptr) {
+             View<bf16> pool = View<bf16>{nullptr, 0, 0}, bool *pooled = nullptr, uint8_t *parg = nullptr) {
   if (pooled) *pooled = false;
   if (c.KS == 3 && c.relu && direct_ok(n, g, c.Cin, c.Cout, true)) {
     DConv p{};
@@ -345,6 +347,7 @@ int conv_fwd(ws_net *n, const Conv &c, Img g, View<const bf16> in, View<bf16> ou
     p.bias = n->params + c.b_off;
     p.y = out;
     p.pool = pool;
+    p.parg = parg;
     if (pooled) *pooled = pool.p != nullptr;
     if (c.Cin == 8) launch_dconv<false, true>(n, p);
     else launch_dconv<false, false>(n, p);
@@ -666,8 +669,9 @@ int forward(ws_net *n, const float *x, int B, bool head = true) {
     View<bf16> eout = l < L - 1 ? mv(n->cat[l], C) : mv(n->bott);
     bool pooled = false;
     rc = conv_fwd(n, n->e2[l], g, cv(n->mid_e[l]), eout, l < L - 1 ? mv(n->pool[l + 1]) : View<bf16>{nullptr, 0, 0},
-                  &pooled);
+                  &pooled, l < L - 1 ? n->parg[l + 1].p : nullptr);
     if (rc) return rc;
+    if (l < L - 1) n->pool_fused[l + 1] = pooled;
     if (l < L - 1 && !pooled) {
       const int64_t cnt = (int64_t)B * (g.H / 2) * (g.W / 2) * (C / 8);  // 8 channels per thread
       hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, g,
@@ -796,8 +800,12 @@ int backward(ws_net *n, const float *target, int B) {
       Img gp = Img::make(B, imgH(n, l - 1), imgW(n, l - 1));
       const int Cp = chans(n, l - 1);
       const int64_t cnt = (int64_t)B * g.H * g.W * Cp;
-      hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, gp, cv(n->cat[l - 1], Cp), Cp,
-                         cv(n->dpool[l]), mv(n->dcat[l - 1], Cp));
+      if (n->pool_fused[l])
+        hipLaunchKernelGGL(k_pool_bwd_arg, dim3(blocks(cnt)), dim3(256), 0, n->stream, gp,
+                           (const uint8_t *)n->parg[l].p, Cp, cv(n->dpool[l]), mv(n->dcat[l - 1], Cp));
+      else
+        hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(cnt)), dim3(256), 0, n->stream, gp, cv(n->cat[l - 1], Cp), Cp,
+                           cv(n->dpool[l]), mv(n->dcat[l - 1], Cp));
     }
   }
   rc = side_join(n);
@@ -886,6 +894,8 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
   wcopies(n->head.Wt, n->head.WtT, n->head.nw());
   // activations and gradients
   n->pool.resize(L);
+  n->parg.resize(L);
+  n->pool_fused.assign(L, 0);
   n->dpool.resize(L);
   n->mid_e.resize(L);
   n->dmid_e.resize(L);
@@ -900,6 +910,7 @@ int ws_create(const ws_config *c, void *hip_stream, ws_net **out) {
     const int C = chans(n, l);
     if (l > 0) {
       rc = buf(n, n->pool[l], l, chans(n, l - 1));
+      if (!rc) rc = buf(n, n->parg[l], l, chans(n, l - 1));
       if (!rc) rc = buf(n, n->dpool[l], l, chans(n, l - 1));
     }
     if (!rc) rc = buf(n, n->mid_e[l], l, C);
