@@ -85,6 +85,11 @@ CASES = [
     # tiles padded to 64 and 256; the latter needs more than 64 KB of LDS)
     (2, 64, 16, 32, 2),
     (2, 136, 16, 32, 1),
+    # deep nets: five and six levels (direct kernels on the levels whose
+    # images are whole tiles, the implicit GEMM below; one side-stream fork
+    # per level)
+    (5, 8, 128, 128, 1),
+    (6, 8, 256, 256, 1),
 ]
 
 
@@ -189,7 +194,7 @@ def test_training_reduces_loss():
 
 
 EXACT = [(2, 8, 16, 32, 2, 4), (3, 24, 32, 32, 2, 2), (2, 32, 16, 64, 2, 4), (3, 32, 32, 64, 1, 2),
-         (4, 32, 128, 256, 1, 2), (2, 64, 16, 32, 2, 4)]
+         (4, 32, 128, 256, 1, 2), (2, 64, 16, 32, 2, 4), (5, 8, 128, 128, 1, 4)]
 
 
 @pytest.mark.parametrize("L,base,H,W,B,cout", EXACT)
