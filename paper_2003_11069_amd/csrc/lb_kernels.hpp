@@ -212,17 +212,32 @@ __device__ __forceinline__ Offs make_offs(int nx, int ny, int nz, int walls, int
 #ifndef LBNCI_NT
 #define LBNCI_NT 0
 #endif
+// The default path is a raw buffer store: the 64-bit base sits in a scalar
+// descriptor and the 32-bit byte offset in the instruction's vector offset.  A
+// global store would need a 64-bit vector address add per store whenever the
+// offset's zero extension was computed in another basic block (every store of
+// the collision loop follows a conditional wall store).  The descriptor's
+// extent is the whole 32-bit offset range, so no in-range store is dropped.
 template <int LEVEL, typename T>
 __device__ __forceinline__ void stb_out(T *base, uint32_t byte_off, T v) {
-  char *p = reinterpret_cast<char *>(base) + (size_t)byte_off;
   if constexpr (LBNCI_NT >= LEVEL) {
+    char *p = reinterpret_cast<char *>(base) + (size_t)byte_off;
     if constexpr (sizeof(T) == 2) {
       __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t *>(p));
     } else {
       __builtin_nontemporal_store(v, reinterpret_cast<T *>(p));
     }
   } else {
-    *reinterpret_cast<T *>(p) = v;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, -1, 0x00020000);
+    if constexpr (sizeof(T) == 2) {
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, byte_off, 0, 0);
+    } else if constexpr (sizeof(T) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, byte_off, 0, 0);
+    } else {
+      static_assert(sizeof(T) == 8, "stb_out: 2-, 4- or 8-byte elements");
+      using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, 0);
+    }
   }
 }
 
@@ -327,6 +342,48 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
 // scalars are staged in LDS with a one-node halo (each is read by up to Q
 // neighbours).  Safe to call repeatedly from one block (persistent kernels):
 // it synchronises before reusing the LDS tile and never returns early.
+// LDS staging of a tile of ROWS rows of 64 + 2H nodes (x fastest; tile slot
+// lx + (64 + 2H) r) whose first column is node x0 - H.  Each wave loads whole
+// rows: 64 consecutive nodes of row r = wave + k (NT / 64), its global row
+// base computed once per row in scalar registers, so an element costs no
+// vector index arithmetic; the 2H halo columns of every row are loaded by
+// the first ROWS 2H threads.  All loads of a thread are issued before its
+// LDS writes.  row(r) returns the global index of node x = 0 of tile row r;
+// load(p, gx) reads the element(s) of node gx of the row that starts at
+// global index p; store(slot, v) writes them to LDS.  near: every x
+// coordinate lies within one period of the lattice (one-step wrap), else
+// modulo.
+template <int H, int ROWS, int NT, typename Row, typename Load, typename Store>
+__device__ __forceinline__ void fill_rows(int tid, int x0, int nx, bool near, Row row, Load load,
+                                          Store store) {
+  constexpr int LXR = 64 + 2 * H, NWV = NT / 64, RIT = (ROWS + NWV - 1) / NWV;
+  static_assert(NT % 64 == 0, "fill_rows: whole waves");
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int gxi = near ? wrap_near(x0 + lane, nx) : wrapi(x0 + lane, nx);
+  using V = decltype(load(0u, 0));
+  V v[RIT];
+#pragma unroll
+  for (int k = 0; k < RIT; ++k) {
+    const int r = wave + k * NWV;
+    if (ROWS % NWV == 0 || r < ROWS) v[k] = load(row(r), gxi);
+  }
+  // halo columns: thread t < ROWS 2H takes row t / 2H, column j = t % 2H
+  // (j < H: left halo, slot j; else right halo, slot 64 + j)
+  const bool hal = tid < ROWS * 2 * H;
+  const int hr = tid / (2 * H), hj = tid % (2 * H), hlx = hj < H ? hj : 64 + hj;
+  V vh{};
+  if (hal) {
+    const int gxh = near ? wrap_near(x0 + hlx - H, nx) : wrapi(x0 + hlx - H, nx);
+    vh = load(row(hr), gxh);
+  }
+#pragma unroll
+  for (int k = 0; k < RIT; ++k) {
+    const int r = wave + k * NWV;
+    if (ROWS % NWV == 0 || r < ROWS) store(lane + H + LXR * r, v[k]);
+  }
+  if (hal) store(hlx + LXR * hr, vh);
+}
+
 template <int D, int TZP, int PBY = 4>
 struct PhaseTile {
   static constexpr int PX = 66, PY = PBY + 2, PZ = (D == 3) ? TZP + 2 : 1;
@@ -353,46 +410,31 @@ __device__ __forceinline__ void phase_tile(const Args<S, R> &A, int bx, int by, 
     // all loads of a thread before its LDS writes; one-step wraps on lattices
     // at least a tile plus halo wide (block-uniform test), else modulo
     __syncthreads();
-    constexpr int IT = (TS + NT - 1) / NT;
-    auto fill = [&](auto wrap) {
-      R va[IT];
-      float vb[IT][D];
-      // tile coordinates of element k = tid + m NT, advanced by NT per step
-      int lx = tid % PX, ly = (tid / PX) % PY, lz = tid / (PX * PY);
-#pragma unroll
-      for (int m = 0; m < IT; ++m) {
-        const int k = tid + m * NT;
-        if (m > 0) {
-          lx += NT % PX;
-          ly += (NT / PX) % PY;
-          lz += NT / (PX * PY);
-          if (lx >= PX) { lx -= PX; ++ly; }
-          if (ly >= PY) { ly -= PY; ++lz; }
-        }
-        if (k < TS) {
-          const int gxx = wrap(x0 + lx - 1, A.nx);
-          const int gyy = wrap(y0 + ly - 1, A.ny);
-          const int gzz = (D == 3) ? wrap(z0 + lz - 1, A.nz) : 0;
-          const uint32_t g = (uint32_t)gxx + (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz);
-          va[m] = ld(A.in.a, g);
-#pragma unroll
-          for (int d = 0; d < D; ++d) vb[m][d] = ld(A.in.B + (size_t)d * A.N, g);
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < IT; ++m) {
-        const int k = tid + m * NT;
-        if (k < TS) {
-          ta[k] = va[m];
-#pragma unroll
-          for (int d = 0; d < D; ++d) tB[d * TS + k] = vb[m][d];
-        }
-      }
+    const bool near = A.nx >= PX - 1 && A.ny >= PY - 1 && (D == 2 || A.nz >= PZ - 1);
+    auto wrap = [&](int v, int n) { return near ? wrap_near(v, n) : wrapi(v, n); };
+    struct AB {
+      R a;
+      float b[D];
     };
-    if (A.nx >= PX - 1 && A.ny >= PY - 1 && (D == 2 || A.nz >= PZ - 1))
-      fill([](int v, int n) { return wrap_near(v, n); });
-    else
-      fill([](int v, int n) { return wrapi(v, n); });
+    fill_rows<1, PY * PZ, NT>(
+        tid, x0, A.nx, near,
+        [&](int r) -> uint32_t {
+          const int gyy = wrap(y0 + r % PY - 1, A.ny);
+          const int gzz = (D == 3) ? wrap(z0 + r / PY - 1, A.nz) : 0;
+          return (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz);
+        },
+        [&](uint32_t p, int gx) {
+          AB v;
+          v.a = ld(A.in.a + p, (uint32_t)gx);
+#pragma unroll
+          for (int d = 0; d < D; ++d) v.b[d] = ld(A.in.B + (size_t)d * A.N + p, (uint32_t)gx);
+          return v;
+        },
+        [&](int k, const AB &v) {
+          ta[k] = v.a;
+#pragma unroll
+          for (int d = 0; d < D; ++d) tB[d * TS + k] = v.b[d];
+        });
     __syncthreads();
   }
   const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
@@ -521,39 +563,19 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
   // (a block-uniform test picks the one-step wrap over integer modulo).
   __syncthreads();
   {
-    constexpr int FILL = LX * LY * LZ, IT = (FILL + NT - 1) / NT;
-    auto fill = [&](auto wrap) {
-      R v[IT];
-      // tile coordinates of element k = tid + m NT, advanced by NT per step
-      // (no division in the loop)
-      int lx = tid % LX, ly = (tid / LX) % LY, lz = tid / (LX * LY);
-#pragma unroll
-      for (int m = 0; m < IT; ++m) {
-        const int k = tid + m * NT;
-        if (m > 0) {
-          lx += NT % LX;
-          ly += (NT / LX) % LY;
-          lz += NT / (LX * LY);
-          if (lx >= LX) { lx -= LX; ++ly; }
-          if (ly >= LY) { ly -= LY; ++lz; }
-        }
-        if (k < FILL) {
-          const int gxx = wrap(x0 + lx - H, A.nx);
-          int gyy = y0 + ly - H;
+    const bool near = A.nx >= LX - H && A.ny >= LY - H && (D == 2 || A.nz >= LZ - H);
+    auto wrap = [&](int v, int n) { return near ? wrap_near(v, n) : wrapi(v, n); };
+    fill_rows<H, LY * LZ, NT>(
+        tid, x0, A.nx, near,
+        [&](int r) -> uint32_t {
+          int gyy = y0 + r % LY - H;
           if (A.walls) gyy = gyy < 1 ? 1 : (gyy > A.ny - 2 ? A.ny - 2 : gyy);
           else gyy = wrap(gyy, A.ny);
-          const int gzz = (D == 3) ? wrap(z0 + lz - H, A.nz) : 0;
-          v[m] = ld(A.psi, (uint32_t)gxx + (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz));
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < IT; ++m)
-        if (tid + m * NT < FILL) tile[tid + m * NT] = v[m];
-    };
-    if (A.nx >= LX - H && A.ny >= LY - H && (D == 2 || A.nz >= LZ - H))
-      fill([](int v, int n) { return wrap_near(v, n); });
-    else
-      fill([](int v, int n) { return wrapi(v, n); });
+          const int gzz = (D == 3) ? wrap(z0 + r / LY - H, A.nz) : 0;
+          return (uint32_t)A.nx * ((uint32_t)gyy + (uint32_t)A.ny * gzz);
+        },
+        [&](uint32_t p, int gx) { return ld(A.psi + p, (uint32_t)gx); },
+        [&](int k, R v) { tile[k] = v; });
   }
   __syncthreads();
 
@@ -784,9 +806,17 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       for (int i = 0; i < L::REST; ++i) {
         const int io = L::opp(i);
         const int icx = L::cx(i), icy = L::cy(i), icz = L::cz(i);
-        const float cu = (float)icx * uf[0] + (float)icy * uf[1] + (float)icz * uf[2];
-        const float cuF = (float)icx * uFf[0] + (float)icy * uFf[1] + (float)icz * uFf[2];
-        const float cG = (float)icx * Ghf[0] + (float)icy * Ghf[1] + (float)icz * Ghf[2];
+        // c.v over the nonzero components only, left to right (a zero
+        // component's product would still cost an instruction)
+        auto cdot = [&](const float *v) -> float {
+          float t = 0.f;
+          bool any = false;
+          if (icx) { t = icx > 0 ? v[0] : -v[0]; any = true; }
+          if (icy) { t = any ? (icy > 0 ? t + v[1] : t - v[1]) : (icy > 0 ? v[1] : -v[1]); any = true; }
+          if (icz) t = any ? (icz > 0 ? t + v[2] : t - v[2]) : (icz > 0 ? v[2] : -v[2]);
+          return t;
+        };
+        const float cu = cdot(uf), cuF = cdot(uFf), cG = cdot(Ghf);
         const float Ae = 4.5f * cu * cu - 1.5f * uu;
         const float AF = 4.5f * cuF * cuF - 1.5f * uuF;
         const float C = cdr + rhof * (AF + om1 * Ae) + pg * (cG * cG);
