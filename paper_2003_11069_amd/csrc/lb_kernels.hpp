@@ -37,6 +37,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace lbk {
 
@@ -278,9 +279,9 @@ __device__ __forceinline__ uint32_t source(const Wrap &w, uint32_t n, int cx, in
 // source in a wall row means bounce-back, i.e. the node's own scalars with the
 // colour term's sign flipped (c_opp(i) = -c_i).
 template <int D, typename S, typename R, int SRC, int COL, bool WANT_C1, int PX = 1, int PY = 1,
-          int TS = 1, int GEOM = 0>
+          int TS = 1, int GEOM = 0, typename FT = float>
 __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, uint32_t n,
-                                     const R *ta, const float *tB, int lidx, float *f, R *c1out,
+                                     const R *ta, const float *tB, int lidx, FT *f, R *c1out,
                                      R &dr, R &r1, R *j, uint32_t gm = 0u) {
   using L = Lat<D>;
   constexpr uint32_t SB = sizeof(S);
@@ -294,13 +295,19 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
     const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
     const R wi = (R)L::w(i);
     float sv;
+    S raw{};
     R c1 = 0;
     if (SRC == EXPLICIT) {
       sv = (float)A.xt[(size_t)i * A.N + n];
+      raw = from_f<S>(sv);
       if (COL != COL_NONE) c1 = (R)A.xc[(size_t)i * A.N + n];
     } else {
-      if (!is_fp32<S>::value && i == L::REST) sv = ld(A.in.s0, n);
-      else sv = to_f(ldb(dir_base(A.in.s, A.N, i), nb + of.x[cx + 1] + of.y[cy + 1] + of.z[cz + 1]));
+      if (!is_fp32<S>::value && i == L::REST) {
+        sv = ld(A.in.s0, n);
+      } else {
+        raw = ldb(dir_base(A.in.s, A.N, i), nb + of.x[cx + 1] + of.y[cy + 1] + of.z[cz + 1]);
+        sv = to_f(raw);
+      }
       if (COL != COL_NONE) {
         const bool bb = GEOM ? ((gm >> i) & 1u) != 0u
                              : (A.walls && cy != 0 && (y - cy == 0 || y - cy == A.ny - 1));
@@ -325,7 +332,11 @@ __device__ __forceinline__ void pull(const Args<S, R> &A, int x, int y, int z, u
         c1 = av * ((R)1 + (R)sv) + cB;
       }
     }
-    f[i] = sv;
+    // f: the deviations as loaded (FT = S keeps them in their stored type, so
+    // that the collision converts each inside its own fused multiply-add; the
+    // rest slot of 16-bit storage is then not returned)
+    if constexpr (std::is_same<FT, float>::value) f[i] = sv;
+    else f[i] = raw;
     if (WANT_C1) c1out[i] = c1;
     const R svr = (R)sv;
     dr += wi * svr;
@@ -718,7 +729,9 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       continue;
     }
 
-    float f[Q];
+    // the collision takes the deviations in their stored type (see pull)
+    using FT = std::conditional_t<(MODE == STEP || MODE == STEP_OBS) && SRC == PULL, S, float>;
+    FT f[Q];
     R c1[Q], dr, r1, j[3];
     if (MODE == POPS)
       pull<D, S, R, SRC, COL_GLOBAL, true, 1, 1, 1, GEOM>(A, x, y, z, n, nullptr, nullptr, 0, f, c1, dr, r1,
@@ -798,9 +811,31 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       // phase are O(1 - 1/gamma), so this rounding matches their storage's)
       const float dnrf = (float)(r1 * A.dr_g1 + (rho - r1) * A.dr_g2);
       const float cdr = om * (drf + dnrf) - pg * (1.0f / 3.0f);
+      // When the moments are FP32 (16-bit storage, whose step is bound by
+      // instruction issue, and the FP32-arithmetic variant) C is evaluated as
+      // a constant plus a quadratic form in c and O as a linear form; the
+      // FP64-moment path and device geometries keep the per-direction form
+      // above (same values up to FP32 rounding):
+      //   C = K + c^T M c,  K = cdr - 1.5 rho (uF.uF + (om-1) u.u),
+      //   M = 4.5 rho (uF uF^T + (om-1) u u^T) + pg G^ G^T,
+      //   O = c.V,  V = 3 rho (uF + (om-1) u).
+      // M's diagonal Md, its doubled off-diagonal entries Mo (xy, xz, yz) and
+      // V are formed once per node; a direction's C is K plus Md of its
+      // nonzero components plus Mo with the sign c_a c_b, summed in a fixed
+      // order so that pairs share their partial sums.
+      const float hq = 4.5f * rhof, hqo = hq * om1, r3 = 3.f * rhof;
+      const float K = cdr - 1.5f * rhof * (uuF + om1 * uu);
+      auto mq = [&](int a, int b) {
+        return hq * uFf[a] * uFf[b] + hqo * uf[a] * uf[b] + pg * Ghf[a] * Ghf[b];
+      };
+      const float Md[3] = {mq(0, 0), mq(1, 1), (D == 3) ? mq(2, 2) : 0.f};
+      const float Mo[3] = {2.f * mq(0, 1), (D == 3) ? 2.f * mq(0, 2) : 0.f, (D == 3) ? 2.f * mq(1, 2) : 0.f};
+      const float V[3] = {r3 * (uFf[0] + om1 * uf[0]), r3 * (uFf[1] + om1 * uf[1]),
+                          (D == 3) ? r3 * (uFf[2] + om1 * uf[2]) : 0.f};
       const uint32_t nb = n * (uint32_t)sizeof(S);
       Offs go{};  // geometry: wrapped byte offsets of the neighbours (periodic)
       if constexpr (GEOM) go = make_offs<D, (uint32_t)sizeof(S)>(A.nx, A.ny, A.nz, 0, x, y, z);
+      constexpr bool QF = std::is_same<R, float>::value && !GEOM;
       R sum_q = 0;
 #pragma unroll
       for (int i = 0; i < L::REST; ++i) {
@@ -816,13 +851,29 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
           if (icz) t = any ? (icz > 0 ? t + v[2] : t - v[2]) : (icz > 0 ? v[2] : -v[2]);
           return t;
         };
-        const float cu = cdot(uf), cuF = cdot(uFf), cG = cdot(Ghf);
-        const float Ae = 4.5f * cu * cu - 1.5f * uu;
-        const float AF = 4.5f * cuF * cuF - 1.5f * uuF;
-        const float C = cdr + rhof * (AF + om1 * Ae) + pg * (cG * cG);
-        const float O = 3.f * rhof * (cuF + om1 * cu);
-        const float sn_i = omc * f[i] + C + O;
-        const float sn_o = omc * f[io] + C - O;
+        float sn_i, sn_o;
+        if constexpr (QF) {
+          float C = K;
+          if (icx) C += Md[0];
+          if (icy) C += Md[1];
+          if (icz) C += Md[2];
+          if (icx && icy) C = (icx == icy) ? C + Mo[0] : C - Mo[0];
+          if (icx && icz) C = (icx == icz) ? C + Mo[1] : C - Mo[1];
+          if (icy && icz) C = (icy == icz) ? C + Mo[2] : C - Mo[2];
+          const float O = cdot(V);
+          // one fused multiply-add per direction (with 16-bit storage it also
+          // converts the stored deviation and rounds the result to 16 bits)
+          sn_i = omc * to_f(f[i]) + (C + O);
+          sn_o = omc * to_f(f[io]) + (C - O);
+        } else {
+          const float cu = cdot(uf), cuF = cdot(uFf), cG = cdot(Ghf);
+          const float Ae = 4.5f * cu * cu - 1.5f * uu;
+          const float AF = 4.5f * cuF * cuF - 1.5f * uuF;
+          const float C = cdr + rhof * (AF + om1 * Ae) + pg * (cG * cG);
+          const float O = 3.f * rhof * (cuF + om1 * cu);
+          sn_i = omc * to_f(f[i]) + C + O;
+          sn_o = omc * to_f(f[io]) + C - O;
+        }
         const S q_i = from_f<S>(sn_i), q_o = from_f<S>(sn_o);
         stb_out<1>(dir_base(A.out.s, A.N, i), nb, q_i);
         stb_out<1>(dir_base(A.out.s, A.N, io), nb, q_o);
