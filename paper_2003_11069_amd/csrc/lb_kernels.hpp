@@ -79,6 +79,40 @@ template <> __device__ __forceinline__ __half from_f<__half>(float v) { return _
 template <> __device__ __forceinline__ __hip_bfloat16 from_f<__hip_bfloat16>(float v) {
   return __float2bfloat16(v);
 }
+// from_f<S>(a * to_f(b) + c) rounded once.  For FP16 a mixed-precision FMA
+// that reads b as FP16 and rounds its result once to FP16; written out so that
+// b need not be converted to FP32 first when it was loaded in another basic
+// block (the compiler forms the same instruction only within one block).
+template <typename S>
+__device__ __forceinline__ S fma_to(float a, S b, float c) {
+  if constexpr (std::is_same<S, __half>::value) {
+    _Float16 r;
+    asm("v_fma_mixlo_f16 %0, %1, %2, %3 op_sel_hi:[0,1,0]"
+        : "=v"(r)
+        : "v"(a), "v"(__builtin_bit_cast(_Float16, b)), "v"(c));
+    return __builtin_bit_cast(__half, r);
+  } else {
+    return from_f<S>(a * to_f(b) + c);
+  }
+}
+
+// (R)a + (R)b of two stored deviations.  For FP16 pairs with FP32 moments a
+// single mixed-precision FMA (a x 1 + b, both read as FP16) gives the same
+// value as two conversions and an add: the sum of two FP16 values is rounded
+// once to FP32 either way.
+template <typename R, typename S>
+__device__ __forceinline__ R pair_sum(S a, S b) {
+  if constexpr (std::is_same<S, __half>::value && std::is_same<R, float>::value) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]"
+        : "=v"(r)
+        : "v"(__builtin_bit_cast(_Float16, a)), "v"(__builtin_bit_cast(_Float16, b)));
+    return r;
+  } else {
+    return (R)to_f(a) + (R)to_f(b);
+  }
+}
+
 template <typename S> struct is_fp32 { static constexpr bool value = false; };
 template <> struct is_fp32<float> { static constexpr bool value = true; };
 
@@ -851,7 +885,7 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
           if (icz) t = any ? (icz > 0 ? t + v[2] : t - v[2]) : (icz > 0 ? v[2] : -v[2]);
           return t;
         };
-        float sn_i, sn_o;
+        S q_i, q_o;
         if constexpr (QF) {
           float C = K;
           if (icx) C += Md[0];
@@ -863,18 +897,17 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
           const float O = cdot(V);
           // one fused multiply-add per direction (with 16-bit storage it also
           // converts the stored deviation and rounds the result to 16 bits)
-          sn_i = omc * to_f(f[i]) + (C + O);
-          sn_o = omc * to_f(f[io]) + (C - O);
+          q_i = fma_to<S>(omc, f[i], C + O);
+          q_o = fma_to<S>(omc, f[io], C - O);
         } else {
           const float cu = cdot(uf), cuF = cdot(uFf), cG = cdot(Ghf);
           const float Ae = 4.5f * cu * cu - 1.5f * uu;
           const float AF = 4.5f * cuF * cuF - 1.5f * uuF;
           const float C = cdr + rhof * (AF + om1 * Ae) + pg * (cG * cG);
           const float O = 3.f * rhof * (cuF + om1 * cu);
-          sn_i = omc * to_f(f[i]) + C + O;
-          sn_o = omc * to_f(f[io]) + C - O;
+          q_i = from_f<S>(omc * to_f(f[i]) + C + O);
+          q_o = from_f<S>(omc * to_f(f[io]) + C - O);
         }
-        const S q_i = from_f<S>(sn_i), q_o = from_f<S>(sn_o);
         stb_out<1>(dir_base(A.out.s, A.N, i), nb, q_i);
         stb_out<1>(dir_base(A.out.s, A.N, io), nb, q_o);
         // populations heading into a wall: reflected copy into the wall row,
@@ -897,7 +930,7 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
           if ((icy == -1 && low) || (icy == 1 && high)) ghost(i, icx, icy, icz, q_i);
           if ((icy == 1 && low) || (icy == -1 && high)) ghost(io, -icx, -icy, -icz, q_o);
         }
-        sum_q += (R)L::w(i) * ((R)to_f(q_i) + (R)to_f(q_o));
+        sum_q += (R)L::w(i) * pair_sum<R>(q_i, q_o);
       }
       const float srest = (float)((dr - sum_q) * (R)(1.0 / L::w(L::REST)));
       if (is_fp32<S>::value) stb_out<1>(dir_base(A.out.s, A.N, L::REST), nb, from_f<S>(srest));
