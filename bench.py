@@ -326,7 +326,7 @@ def bench_sweep(a):
     out = {"metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(el / a.steps * 1e3, 5), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp32": "f64", "fp16": "f32", "bf16": "f32", "fp32_f32": "f32"}[a.storage],
+           "dtype": "fp32",
            "data": "synthetic (seeded channel sweep)",
            "config": {"workload": "64 D2Q9 channels, Lx 256..1024, Ly 64..160, seeded sweep",
                       "channels": len(ps), "fluid_nodes": fluid, "storage": a.storage, "mode": a.mode,
@@ -406,7 +406,7 @@ def bench_geometry(a):
     out = {"metric": "MLUPS with a node-type geometry", "value": round(mlups, 2), "unit": "MLUPS",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(el / a.steps * 1e3, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp32": "f64", "fp16": "f32", "bf16": "f32", "fp32_f32": "f32"}[a.storage],
+           "dtype": "fp32",
            "data": "synthetic (seeded droplet packing)",
            "config": {"workload": "D3Q27 droplet channel 256x64x64, wall rows as solid nodes",
                       "fluid_nodes": fluid, "storage": a.storage},
@@ -427,7 +427,7 @@ def bench_focuser(a):
     out = {"metric": "flow-focuser droplet generation", "value": round(mlups, 2), "unit": "MLUPS",
            "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(r["seconds"] / steps * 1e3, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp32": "f64", "fp16": "f32", "bf16": "f32", "fp32_f32": "f32"}[a.storage],
+           "dtype": "fp32",
            "data": "synthetic (flow-focuser geometry, inlet speeds)",
            "config": {"workload": f"D2Q9 flow-focuser {r['nx']}x{r['ny']}, phi {r['phi']}",
                       "storage": a.storage},
