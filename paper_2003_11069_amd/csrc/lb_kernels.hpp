@@ -403,6 +403,7 @@ __device__ __forceinline__ void fill_rows(int tid, int x0, int nx, bool near, Ro
                                           Store store) {
   constexpr int LXR = 64 + 2 * H, NWV = NT / 64, RIT = (ROWS + NWV - 1) / NWV;
   static_assert(NT % 64 == 0, "fill_rows: whole waves");
+  static_assert(ROWS * 2 * H <= NT, "fill_rows: one halo element per thread");
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int gxi = near ? wrap_near(x0 + lane, nx) : wrapi(x0 + lane, nx);
   using V = decltype(load(0u, 0));
