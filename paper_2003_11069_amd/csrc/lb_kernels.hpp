@@ -584,6 +584,10 @@ __device__ __forceinline__ void main_decode(int nx, int ny, int lb, int &bx, int
   bz = lb / (gx * gy);
 }
 
+// integer probe: up to this many samples are read together (longer probes
+// take the sample-by-sample loop)
+constexpr int PROBE_MAX = 4;
+
 template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int NCI = 0,
           int GEOM = 0>
 __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, int bz, int slot,
@@ -706,6 +710,39 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       }
       if (hit) {
         const R Ah = strength_shifted<R>(hc, A.A, A.h_min, A.h_max);
+        Fr[0] = -Ah * nn[0] * (R)0.5 * g;
+        Fr[1] = -Ah * nn[1] * (R)0.5 * g;
+        Fr[2] = -Ah * nn[2] * (R)0.5 * g;
+      }
+    } else if (NCI == 0 && A.A > (R)0 && g > (R)0 && !GEOM && A.smax <= PROBE_MAX) {
+      // up to PROBE_MAX samples: all of them read at once from the global psi
+      // array (L2-resident; the row index clamped into the lattice, so every
+      // read is in bounds), so the reads do not wait for one another; then
+      // the first sample at or above psi(x) before a wall or smax is the hit
+      const R ps = T(0, 0, 0);
+      const R nn[3] = {-Gh[0], -Gh[1], -Gh[2]};
+      R pv[PROBE_MAX];
+      bool ok[PROBE_MAX];
+#pragma unroll
+      for (int k = 0; k < PROBE_MAX; ++k) {
+        const int s = k + 1;
+        const int ox = (int)round_away((R)s * nn[0]);
+        const int oy = (int)round_away((R)s * nn[1]);
+        const int oz = (D == 3) ? (int)round_away((R)s * nn[2]) : 0;
+        const int yt = y + oy;
+        ok[k] = s <= A.smax && !(A.walls && (yt <= 0 || yt >= A.ny - 1));
+        const int xt = wrapp(x + ox, A.nx);
+        const int ytt = A.walls ? min(max(yt, 1), A.ny - 2) : wrapp(yt, A.ny);
+        const int zt = (D == 3) ? wrapp(z + oz, A.nz) : 0;
+        pv[k] = ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)ytt + (uint32_t)A.ny * zt));
+      }
+#pragma unroll
+      for (int k = 0; k < PROBE_MAX; ++k) {
+        if (!ok[k]) break;
+        if (pv[k] >= ps) { hit = k + 1; break; }
+      }
+      if (hit) {
+        const R Ah = strength<R>(hit, A.A, A.h_min, A.h_max);
         Fr[0] = -Ah * nn[0] * (R)0.5 * g;
         Fr[1] = -Ah * nn[1] * (R)0.5 * g;
         Fr[2] = -Ah * nn[2] * (R)0.5 * g;
