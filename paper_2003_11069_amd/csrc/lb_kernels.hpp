@@ -721,6 +721,11 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       // the first sample at or above psi(x) before a wall or smax is the hit
       const R ps = T(0, 0, 0);
       const R nn[3] = {-Gh[0], -Gh[1], -Gh[2]};
+      // every sample up to PROBE_MAX is read (also those beyond smax), so the
+      // one-step wrap needs lattices longer than PROBE_MAX in every periodic
+      // direction (a block-uniform test; integer modulo otherwise)
+      const bool wrapb = A.nx > PROBE_MAX && A.ny > PROBE_MAX && (D == 2 || A.nz > PROBE_MAX);
+      auto wrapq = [&](int v, int n) { return wrapb ? wrap_near(v, n) : wrapi(v, n); };
       R pv[PROBE_MAX];
       bool ok[PROBE_MAX];
 #pragma unroll
@@ -731,9 +736,9 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         const int oz = (D == 3) ? (int)round_away((R)s * nn[2]) : 0;
         const int yt = y + oy;
         ok[k] = s <= A.smax && !(A.walls && (yt <= 0 || yt >= A.ny - 1));
-        const int xt = wrapp(x + ox, A.nx);
-        const int ytt = A.walls ? min(max(yt, 1), A.ny - 2) : wrapp(yt, A.ny);
-        const int zt = (D == 3) ? wrapp(z + oz, A.nz) : 0;
+        const int xt = wrapq(x + ox, A.nx);
+        const int ytt = A.walls ? min(max(yt, 1), A.ny - 2) : wrapq(yt, A.ny);
+        const int zt = (D == 3) ? wrapq(z + oz, A.nz) : 0;
         pv[k] = ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)ytt + (uint32_t)A.ny * zt));
       }
 #pragma unroll
