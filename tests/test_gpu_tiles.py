@@ -8,8 +8,11 @@ coordinate wraps by the largest amount.  The one-step bounds: D3Q27 k_main
 (64 x 4 x 1 tiles, halo 1) nx >= 65, ny >= 5, nz >= 2; k_phase (64 x 4 tiles,
 2 planes with FP32 storage, 4 with 16-bit storage) nx >= 65, ny >= 5, nz >= 3
 (FP32) or 5 (16-bit); D2Q9 k_main (halo 4) nx >= 68, ny >= 8 and k_phase
-nx >= 65, ny >= 5.  Each case below sits on or one node below a bound and
-runs against the FP64 oracle with NCI active, periodic or with walls.
+nx >= 65, ny >= 5.  The integer NCI probe reads its first four samples
+together and wraps them by one step on lattices longer than four nodes in
+every periodic direction (ny = nz = 5 below is on that bound, nz = 2..4
+below it).  Each case below sits on or one node below a bound and runs
+against the FP64 oracle with NCI active, periodic or with walls.
 """
 import pytest
 
