@@ -79,10 +79,11 @@ template <> __device__ __forceinline__ __half from_f<__half>(float v) { return _
 template <> __device__ __forceinline__ __hip_bfloat16 from_f<__hip_bfloat16>(float v) {
   return __float2bfloat16(v);
 }
-// from_f<S>(a * to_f(b) + c) rounded once.  For FP16 a mixed-precision FMA
-// that reads b as FP16 and rounds its result once to FP16; written out so that
-// b need not be converted to FP32 first when it was loaded in another basic
-// block (the compiler forms the same instruction only within one block).
+// a * b + c as a fused multiply-add, stored as S.  For FP16 a mixed-precision
+// FMA that reads b as FP16 and rounds its result once, to FP16 (the form the
+// compiler itself emits for this expression within one basic block); written
+// out so that b need not be converted to FP32 first when it was loaded in
+// another block.  Other types round the FP32 result to S.
 template <typename S>
 __device__ __forceinline__ S fma_to(float a, S b, float c) {
   if constexpr (std::is_same<S, __half>::value) {
@@ -888,8 +889,8 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       // phase are O(1 - 1/gamma), so this rounding matches their storage's)
       const float dnrf = (float)(r1 * A.dr_g1 + (rho - r1) * A.dr_g2);
       const float cdr = om * (drf + dnrf) - pg * (1.0f / 3.0f);
-      // When the moments are FP32 (16-bit storage, whose step is bound by
-      // instruction issue, and the FP32-arithmetic variant) C is evaluated as
+      // When the moments are FP32 (16-bit storage, whose main pass is close
+      // to its instruction-issue bound, and the FP32-arithmetic variant) C is evaluated as
       // a constant plus a quadratic form in c and O as a linear form; the
       // FP64-moment path and device geometries keep the per-direction form
       // above (same values up to FP32 rounding):
