@@ -586,7 +586,8 @@ __device__ __forceinline__ void main_decode(int nx, int ny, int lb, int &bx, int
 }
 
 // integer probe: up to this many samples are read together (longer probes
-// take the sample-by-sample loop)
+// take the sample-by-sample loop, which with a geometry reads the tile's psi
+// inside the halo)
 constexpr int PROBE_MAX = 4;
 
 template <int D, typename S, typename R, int SRC, int MODE, int BY, int TZ, int H, int NCI = 0,
@@ -715,11 +716,12 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         Fr[1] = -Ah * nn[1] * (R)0.5 * g;
         Fr[2] = -Ah * nn[2] * (R)0.5 * g;
       }
-    } else if (NCI == 0 && A.A > (R)0 && g > (R)0 && !GEOM && A.smax <= PROBE_MAX) {
+    } else if (NCI == 0 && A.A > (R)0 && g > (R)0 && A.smax <= PROBE_MAX) {
       // up to PROBE_MAX samples: all of them read at once from the global psi
       // array (L2-resident; the row index clamped into the lattice, so every
-      // read is in bounds), so the reads do not wait for one another; then
-      // the first sample at or above psi(x) before a wall or smax is the hit
+      // read is in bounds), with a geometry's node-type words, so the reads
+      // do not wait for one another; then the first sample at or above psi(x)
+      // before a wall, a non-fluid node (geometries) or smax is the hit
       const R ps = T(0, 0, 0);
       const R nn[3] = {-Gh[0], -Gh[1], -Gh[2]};
       // every sample up to PROBE_MAX is read (also those beyond smax), so the
@@ -729,6 +731,7 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
       auto wrapq = [&](int v, int n) { return wrapb ? wrap_near(v, n) : wrapi(v, n); };
       R pv[PROBE_MAX];
       bool ok[PROBE_MAX];
+      uint32_t ms[PROBE_MAX] = {};
 #pragma unroll
       for (int k = 0; k < PROBE_MAX; ++k) {
         const int s = k + 1;
@@ -740,11 +743,14 @@ __device__ __forceinline__ void main_tile(const Args<S, R> &A, int bx, int by, i
         const int xt = wrapq(x + ox, A.nx);
         const int ytt = A.walls ? min(max(yt, 1), A.ny - 2) : wrapq(yt, A.ny);
         const int zt = (D == 3) ? wrapq(z + oz, A.nz) : 0;
-        pv[k] = ld(A.psi, (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)ytt + (uint32_t)A.ny * zt));
+        const uint32_t ns = (uint32_t)xt + (uint32_t)A.nx * ((uint32_t)ytt + (uint32_t)A.ny * zt);
+        pv[k] = ld(A.psi, ns);
+        if constexpr (GEOM) ms[k] = ld(A.nbm, ns);
       }
 #pragma unroll
       for (int k = 0; k < PROBE_MAX; ++k) {
         if (!ok[k]) break;
+        if (GEOM && (ms[k] & GEO_NONFLUID)) break;
         if (pv[k] >= ps) { hit = k + 1; break; }
       }
       if (hit) {
