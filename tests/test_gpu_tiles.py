@@ -51,3 +51,21 @@ def test_parity_at_tile_thresholds(lat, nx, ny, nz, walls, storage):
     say(f"  errors {e}")
     tr, tu = BOUNDS[storage]
     assert e["rho1"] <= tr and e["rho2"] <= tr and e["u"] <= tu
+
+
+@pytest.mark.parametrize("nz", [4, 5])
+def test_probe_reads_on_short_periodic_lattices(nz):
+    """Every probe sample live (h_max = 4, so smax = 4) on lattices of four
+    and five nodes in z and five in y, periodic: the batched probe reads wrap
+    by integer modulo at four nodes (offsets up to four reach a full period)
+    and by one step at five."""
+    p = synth.base_params(lattice=1, nx=65, ny=5, nz=nz, walls_y=0, A_nci=0.01, h_min=2.0, h_max=4.0)
+    case = synth.random_fields(p, seed=101 + nz)
+    say(f"[gpu] probe reads, D3Q27 65x5x{nz} periodic, h_max 4, {STEPS} steps")
+    o, g = make_pair(case, storage="fp32")
+    o.step(STEPS)
+    g.step(STEPS)
+    e = field_errors(o, g, fluid_mask(case.params, case.N))
+    say(f"  errors {e}")
+    tr, tu = BOUNDS["fp32"]
+    assert e["rho1"] <= tr and e["rho2"] <= tr and e["u"] <= tu
